@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the ESI hot path on one MI355X.
+
+One step = the whole hot path over one batch: reset the per-pixel state,
+then one esi_integrate_window call that integrates the workload's whole
+event stream (Alg. 2 event loop with the clamp of Eq. (13)) and writes all
+of its frames (Eq. (14), decayed snapshots, FP32).  Inputs are resident in
+HBM before timing starts.
+
+Default workload (c2): 640x480 sensor, 10 s of a seeded random-walk
+translating texture, about 20M events, frames at 100 FPS (1000 frames).
+
+Prints one JSON line on stdout: Gevents/s integrated (value), frames/s,
+the roofline of the dominant kernel (integration, measured with HIP events
+recorded by the library on its stream), the whole-step roofline, the parity
+of this run's output against the FP64 oracle, and the oracle itself timed on
+the host as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n: int, npix: int, nf: int, u8: bool) -> int:
+    """Bytes the method itself must move in one whole-stream call: the events
+    read once (x, y u16, t i64, p i8 = 13 B), the per-pixel state read and
+    written once (S f32, T i64, N u32, P i32 = 20 B each way), every frame
+    written once (4 B per pixel, plus 1 B with 8-bit codes)."""
+    return 13 * n + 40 * npix + (4 + (1 if u8 else 0)) * nf * npix
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--fps", type=float, default=100.0)
+    ap.add_argument("--u8", action="store_true", help="also write 8-bit frames")
+    ap.add_argument("--cpu-sample-s", type=float, default=3.0,
+                    help="seconds of the workload the CPU oracle is timed on")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE "
+              f"{world}): this build measures the single-GPU path; sharding across GPUs "
+              "is described in DESIGN.md and not built.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import evgen
+    import paper_2508_02238_amd as esi
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    s = evgen.preset(args.workload)
+    tf = s.frame_times(args.fps)
+    n, W, H, nf = s.n, s.width, s.height, len(tf)
+    npix = W * H
+    log(f"[bench] workload {args.workload}: {W}x{H}, {n} events, {nf} frames "
+        f"(generated in {time.time() - t0:.1f} s)")
+    prm = dict(evgen.DEFAULT_PARAMS)
+
+    dev = torch.device("cuda", 0)
+    x_d = torch.from_numpy(s.x.view(np.int16)).to(dev)
+    y_d = torch.from_numpy(s.y.view(np.int16)).to(dev)
+    t_d = torch.from_numpy(s.t).to(dev)
+    p_d = torch.from_numpy(s.p).to(dev)
+    tf_d = torch.from_numpy(tf).to(dev)
+    frames = torch.empty((nf, H, W), dtype=torch.float32, device=dev)
+    frames_u8 = torch.empty((nf, H, W), dtype=torch.uint8, device=dev) if args.u8 else None
+    st = esi.State(W, H, **prm)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step():
+        rc = esi.esi_reset(st.handle, stream)
+        assert rc == esi.ESI_OK, esi.esi_status_string(rc)
+        rc = esi.esi_integrate_window(
+            st.handle, x_d.data_ptr(), y_d.data_ptr(), t_d.data_ptr(), p_d.data_ptr(), n,
+            tf_d.data_ptr(), nf, frames.data_ptr(),
+            frames_u8.data_ptr() if frames_u8 is not None else None, stream)
+        assert rc == esi.ESI_OK, esi.esi_status_string(rc)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} steps done")
+
+    assert esi.esi_profile_enable(st.handle, True) == esi.ESI_OK
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    host_ms = (time.perf_counter() - h0) * 1e3
+    gpu_ms = ev0.elapsed_time(ev1)
+    rc, calls, bucket_ms, integ_ms = esi.esi_profile_read(st.handle)
+    assert rc == esi.ESI_OK and calls == args.steps
+    esi.esi_profile_enable(st.handle, False)
+    ms_per_step = gpu_ms / args.steps
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (host {host_ms / args.steps:.3f}), "
+        f"bucketing {bucket_ms / calls:.3f} ms, integration {integ_ms / calls:.3f} ms")
+
+    alg = algorithmic_bytes(n, npix, nf, args.u8)
+    integ_avg_ms = integ_ms / calls
+    roofline = {
+        "kernel": "k_integrate (per-tile event loop + frames)",
+        "bound": "hbm",
+        "achieved": round(alg / (integ_avg_ms * 1e-3) / 1e9, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(alg / (integ_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "algorithmic_bytes": alg,
+        "avg_launch_ms": round(integ_avg_ms, 4),
+    }
+    roofline_path = {
+        "achieved": round(alg / (ms_per_step * 1e-3) / 1e9, 1),
+        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "bucketing_ms": round(bucket_ms / calls, 4),
+    }
+
+    parity = None
+    if not args.no_parity:
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from esi_parity import REL
+        sel = sorted(set([0, nf // 3, nf // 2, nf - 1]))
+        h0 = time.time()
+        o = oracle.State(W, H, oracle.Params(**prm))
+        fo = o.integrate(s.x, s.y, s.t, s.p, t_frames=tf, frame_sel=sel)
+        S, T, N, P = (a.cpu().numpy() for a in st.read_state())
+        fg = frames[sel].cpu().numpy()
+        floor_f = prm["C"] / (prm["s_max"] - prm["s_min"])
+        s_err = np.abs(S.astype(np.float64) - o.S) / np.maximum(np.abs(o.S), prm["C"])
+        f_err = np.abs(fg.astype(np.float64) - fo) / np.maximum(np.abs(fo), floor_f)
+        ok = (np.array_equal(N.view(np.uint32), o.N) and np.array_equal(P, o.P)
+              and np.array_equal(T, o.T) and s_err.max() <= REL and f_err.max() <= REL)
+        parity = {"ok": bool(ok), "max_rel_S": float(s_err.max()),
+                  "max_rel_frame": float(f_err.max()), "frames_checked": sel,
+                  "exact_N_P_T": bool(np.array_equal(N.view(np.uint32), o.N)
+                                      and np.array_equal(P, o.P) and np.array_equal(T, o.T))}
+        log(f"[bench] parity vs oracle: {parity} ({time.time() - h0:.1f} s)")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        m = int(np.searchsorted(s.t, int(args.cpu_sample_s * 1e6), side="left"))
+        tf_s = tf[tf < int(args.cpu_sample_s * 1e6)]
+        o = oracle.State(W, H, oracle.Params(**prm))
+        h0 = time.perf_counter()
+        o.integrate(s.x[:m], s.y[:m], s.t[:m], s.p[:m], t_frames=tf_s)
+        el = time.perf_counter() - h0
+        cpu = {"value": round(m / el / 1e9, 6), "unit": "Gevents/s", "cores": 1,
+               "kind": "oracle",
+               "frames_per_s": round(len(tf_s) / el, 2),
+               "sample": (f"first {args.cpu_sample_s:g} s of the workload: {m} events and "
+                          f"{len(tf_s)} frames, serial FP64 oracle, {el:.1f} s"),
+               "cpu_model": _cpu_model()}
+        log(f"[bench] cpu baseline: {cpu}")
+
+    value = n / (ms_per_step * 1e-3) / 1e9
+    out = {
+        "metric": "Gevents/s integrated + frames/s at 1e-5 rel err",
+        "value": round(value, 3),
+        "unit": "Gevents/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "frames_per_s": round(nf / (ms_per_step * 1e-3), 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {W}x{H}, {s.duration_us / 1e6:g} s, "
+                               f"{n} events, {nf} frames at {args.fps:g} FPS"
+                               + (", +u8 frames" if args.u8 else ""),
+                   "events": n, "frames": nf, "width": W, "height": H,
+                   "params": prm, "frame_dtype": "f32"},
+        "roofline": roofline,
+        "roofline_path": roofline_path,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    st.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical CPUs)"
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,60 @@
+"""The C ABI library loads and exports every entry point include/esi.h
+declares; argument checks that need no GPU."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "esi.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(esi_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("esi_create_state", "esi_integrate_window", "esi_snapshot_frame"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2508_02238_amd as esi
+    out = subprocess.run(["nm", "-D", "--defined-only", esi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (esi_[a-z_]+)\b", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    assert set(esi.EXPORTED) == set(_declared())
+
+
+def test_status_strings():
+    import paper_2508_02238_amd as esi
+    for s in range(5):
+        assert esi.esi_status_string(s).startswith("ESI_")
+    assert "UNKNOWN" in esi.esi_status_string(99)
+
+
+@pytest.mark.parametrize("w,h,kw", [(0, 4, {}), (4, 0, {}), (70000, 4, {}), (4000, 4000, {}),
+                                    (4, 4, dict(C=0.0)), (4, 4, dict(b=0.0)),
+                                    (4, 4, dict(k_per_us=-1e-6)),
+                                    (4, 4, dict(s_min=1.0, s_max=1.0)),
+                                    (4, 4, dict(C=float("nan"))), (4, 4, dict(flags=64))])
+def test_create_rejects_invalid_arguments(w, h, kw):
+    """Checked on the host before any HIP call, so this runs without a GPU."""
+    import paper_2508_02238_amd as esi
+    rc, handle = esi.esi_create_state(w, h, esi.make_params(**kw), 0)
+    assert rc == esi.ESI_ERR_INVALID_ARG and handle is None
+
+
+def test_null_state_is_rejected():
+    import paper_2508_02238_amd as esi
+    assert esi.esi_reset(None, 0) == esi.ESI_ERR_INVALID_ARG
+    assert esi.esi_destroy_state(None) == esi.ESI_ERR_INVALID_ARG
+    assert esi.esi_snapshot_frame(None, 0, None, None, 0) == esi.ESI_ERR_INVALID_ARG
+    assert esi.esi_state_bytes(None) == 0

@@ -50,8 +50,8 @@ def main() -> int:
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--fps", type=float, default=100.0)
     ap.add_argument("--u8", action="store_true", help="also write 8-bit frames")
-    ap.add_argument("--cpu-sample-s", type=float, default=3.0,
-                    help="seconds of the workload the CPU oracle is timed on")
+    ap.add_argument("--cpu-sample-s", type=float, default=0.0,
+                    help="seconds of the workload the CPU oracle is timed on (0: all of it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     args = ap.parse_args()
@@ -168,8 +168,9 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        m = int(np.searchsorted(s.t, int(args.cpu_sample_s * 1e6), side="left"))
-        tf_s = tf[tf < int(args.cpu_sample_s * 1e6)]
+        span_s = args.cpu_sample_s if args.cpu_sample_s > 0 else s.duration_us / 1e6
+        m = int(np.searchsorted(s.t, int(span_s * 1e6), side="left"))
+        tf_s = tf[tf <= int(span_s * 1e6)]
         o = oracle.State(W, H, oracle.Params(**prm))
         h0 = time.perf_counter()
         o.integrate(s.x[:m], s.y[:m], s.t[:m], s.p[:m], t_frames=tf_s)
@@ -177,7 +178,7 @@ def main() -> int:
         cpu = {"value": round(m / el / 1e9, 6), "unit": "Gevents/s", "cores": 1,
                "kind": "oracle",
                "frames_per_s": round(len(tf_s) / el, 2),
-               "sample": (f"first {args.cpu_sample_s:g} s of the workload: {m} events and "
+               "sample": (f"first {span_s:g} s of the workload: {m} events and "
                           f"{len(tf_s)} frames, serial FP64 oracle, {el:.1f} s"),
                "cpu_model": _cpu_model()}
         log(f"[bench] cpu baseline: {cpu}")

@@ -58,8 +58,8 @@ def gpu_run(esi, stream, prm: dict, t_frames=None, calls=None, want_u8=False,
     diag = st.diagnostics()
     st.close()
     # copy only the frames compared (the full set can be tens of GB)
-    frames = torch.cat(frames_all) if frames_all else None
-    u8 = torch.cat(u8_all) if u8_all else None
+    cat = lambda xs: (xs[0] if len(xs) == 1 else torch.cat(xs)) if xs else None
+    frames, u8 = cat(frames_all), cat(u8_all)
     if frame_sel is not None:
         idx = torch.as_tensor(np.asarray(frame_sel), device=frames_all[0].device if frames_all
                               else "cuda")

@@ -54,6 +54,9 @@ def main() -> int:
                     help="seconds of the workload the CPU oracle is timed on (0: all of it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after timing, run one plain device copy of this many MiB (a "
+                         "known-size reference for hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -122,6 +125,15 @@ def main() -> int:
     ms_per_step = gpu_ms / args.steps
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (host {host_ms / args.steps:.3f}), "
         f"bucketing {bucket_ms / calls:.3f} ms, integration {integ_ms / calls:.3f} ms")
+
+    if args.copy_probe_mb:
+        a = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
+        del a, b
 
     alg = algorithmic_bytes(n, npix, nf, args.u8)
     integ_avg_ms = integ_ms / calls

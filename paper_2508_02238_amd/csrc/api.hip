@@ -63,10 +63,6 @@ MethodParams method_params(const esi_params& p)
     mp.s_min = p.s_min;
     mp.s_max = p.s_max;
     mp.inv_range = 1.0 / (p.s_max - p.s_min);
-    mp.b_kind = 0;
-    for (int e = 1; e <= 4; ++e)
-        if (p.b == (double)e)
-            mp.b_kind = e;
     mp.decay_then_add = (p.flags & ESI_DECAY_THEN_ADD) ? 1 : 0;
     mp.lazy = (p.flags & ESI_SNAPSHOT_LAZY) ? 1 : 0;
     return mp;
@@ -295,9 +291,10 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
     CallScratch cs{};
     if (n > 0) {
         const int64_t M = (int64_t)sc.ntiles * sc.nunits;
-        const int64_t nb = (M + kScanBlockItems - 1) / kScanBlockItems;
+        const int seg = scan_segment_units(sc.nunits);
+        const int64_t nseg = (sc.nunits + seg - 1) / seg;
         const size_t o_bs = align_up(4 * (size_t)M, 256);
-        const size_t o_tot = o_bs + align_up(4 * (size_t)nb, 256);
+        const size_t o_tot = o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
         const size_t o_rec = o_tot + 256;
         const size_t need = o_rec + 8 * (size_t)n;
         if (need > st->scratch_bytes) {

@@ -6,16 +6,24 @@
 // consecutive pixels) while keeping array order inside every tile (and so
 // inside every pixel): a counting sort whose ranks are stable.
 //
-//   k_hist     one wave per unit of 2^unit_log events: per-tile counts of the
-//              unit's valid events -> table[unit][tile].  Out-of-range events
-//              are counted as dropped.
-//   k_scan_*   exclusive scan of the table in (tile, unit) order: the offset
-//              of each unit's run inside each tile's bucket.
-//   k_scatter  one wave per unit again: walks its events 64 at a time in
-//              order, ranks each event stably among the same-tile events of
-//              the unit, writes a 64-bit record (time offset, pixel in tile,
-//              polarity) to its slot.  Also flags decreasing times and calls
-//              whose time span does not fit the record.
+//   k_hist      one wave per unit of 2^unit_log consecutive events: per-tile
+//               counts of the unit's valid events -> table[unit][tile];
+//               out-of-range events are counted as dropped.
+//   k_seg_sum,  exclusive scan of the table in (tile, unit) order, done
+//   k_seg_scan, column-wise so every access is a coalesced row access:
+//   k_seg_down  per-tile sums over segments of units, a scan over segments
+//               and tiles, then a rescan of each segment writing offsets.
+//   k_scatter   one wave per unit again: walks its events 64 at a time in
+//               order (8 steps loaded ahead), ranks each event stably among
+//               the same-tile events of the unit, writes a 64-bit record
+//               (time offset, pixel in tile, polarity) to its slot.  Also
+//               flags decreasing times and calls whose span the record cannot
+//               hold.
+//
+// Workgroups are dispatched round-robin over the 8 XCDs; units are assigned
+// so that the workgroups of one XCD take consecutive units.  Consecutive
+// units write adjacent pieces of every tile bucket, so a cache line of a
+// bucket is completed inside one XCD's L2 before it is written back.
 #include <hip/hip_runtime.h>
 
 #include "esi_internal.hpp"
@@ -23,9 +31,19 @@
 namespace esi {
 namespace {
 
-__device__ __forceinline__ bool decode(const EventsDev& ev, int64_t i, int W, int H, uint32_t& q)
+constexpr int kXcds = 8;
+constexpr int kBatch = 8;  // scatter: steps of 64 events loaded ahead
+
+// Bijection blockIdx -> work index that gives each XCD a contiguous range.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 {
-    const uint32_t x = ev.x[i], y = ev.y[i];
+    const int64_t x = b % kXcds, i = b / kXcds;
+    const int64_t q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ bool valid_q(uint32_t x, uint32_t y, int W, int H, uint32_t& q)
+{
     q = y * (uint32_t)W + x;
     return x < (uint32_t)W && y < (uint32_t)H;
 }
@@ -37,7 +55,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int
     extern __shared__ uint32_t lds[];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t unit = blk * kWavesPerBlock + wave;
     uint32_t* h = lds + wave * K;
     for (int k = lane; k < K; k += kWave)
         h[k] = 0;
@@ -46,21 +65,33 @@ __global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int
     if (unit < B) {
         const int64_t lo = unit << unit_log;
         const int64_t hi = min(lo + ((int64_t)1 << unit_log), ev.n);
-        int64_t i = lo + lane;
-        for (; i + 3 * kWave < hi; i += 4 * kWave) {
-            uint32_t q0, q1, q2, q3;
-            const bool v0 = decode(ev, i, W, H, q0);
-            const bool v1 = decode(ev, i + kWave, W, H, q1);
-            const bool v2 = decode(ev, i + 2 * kWave, W, H, q2);
-            const bool v3 = decode(ev, i + 3 * kWave, W, H, q3);
-            if (v0) atomicAdd(&h[q0 >> tile_log], 1u); else ++drop;
-            if (v1) atomicAdd(&h[q1 >> tile_log], 1u); else ++drop;
-            if (v2) atomicAdd(&h[q2 >> tile_log], 1u); else ++drop;
-            if (v3) atomicAdd(&h[q3 >> tile_log], 1u); else ++drop;
+        const bool vec = (((uintptr_t)ev.x | (uintptr_t)ev.y) & 15u) == 0;
+        int64_t i = lo;
+        if (vec) {
+            // 8 events per lane per step: 16-byte loads of x and y
+            for (; i + 8 * kWave <= hi; i += 8 * kWave) {
+                const int64_t e = i + 8 * lane;
+                const uint4 xv = *(const uint4*)(ev.x + e);
+                const uint4 yv = *(const uint4*)(ev.y + e);
+                const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
+                const uint32_t ys[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    uint32_t q;
+                    if (valid_q(xs[m] & 0xFFFFu, ys[m] & 0xFFFFu, W, H, q))
+                        atomicAdd(&h[q >> tile_log], 1u);
+                    else
+                        ++drop;
+                    if (valid_q(xs[m] >> 16, ys[m] >> 16, W, H, q))
+                        atomicAdd(&h[q >> tile_log], 1u);
+                    else
+                        ++drop;
+                }
+            }
         }
-        for (; i < hi; i += kWave) {
+        for (int64_t e = i + lane; e < hi; e += kWave) {
             uint32_t q;
-            if (decode(ev, i, W, H, q))
+            if (valid_q(ev.x[e], ev.y[e], W, H, q))
                 atomicAdd(&h[q >> tile_log], 1u);
             else
                 ++drop;
@@ -76,15 +107,50 @@ __global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int
         atomicAdd(&diag->dropped, (unsigned long long)drop);
 }
 
-// ---- exclusive scan over the table in (tile, unit) order -------------------
-// Element m = k * B + u lives at table[u * K + k].
+// ---- exclusive scan of table[u][k] in (k, u) order, column-wise -------------
+// Segments of `seg` units.  segsum[s][k] = sum over the units of segment s.
 
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_waves,
-                                                         uint32_t& block_total)
+__global__ __launch_bounds__(kBlock) void k_seg_sum(const uint32_t* table, int K, int64_t B,
+                                                    int seg, uint32_t* segsum)
 {
-    // inclusive scan inside the wave
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    const int s = blockIdx.y;
+    if (k >= K)
+        return;
+    const int64_t u0 = (int64_t)s * seg, u1 = min(u0 + seg, B);
+    uint32_t sum = 0;
+    for (int64_t u = u0; u < u1; ++u)
+        sum += table[u * K + k];
+    segsum[(int64_t)s * K + k] = sum;
+}
+
+// One workgroup: per tile, exclusive scan over segments; then the exclusive
+// scan of tile totals gives each tile's start.  segsum[s][k] becomes the
+// offset of (segment s, tile k) in the whole (tile, unit) order.  Each thread
+// owns up to 4 consecutive tiles (K <= 4096).
+__global__ __launch_bounds__(1024) void k_seg_scan(uint32_t* segsum, int K, int nseg,
+                                                   uint32_t* total, DiagDev* diag)
+{
+    __shared__ uint32_t sw[1024 / kWave];
+    const int per = (K + 1023) / 1024;
+    const int k0 = threadIdx.x * per;
+    uint32_t tot[4] = {0u, 0u, 0u, 0u};
+    uint32_t mine = 0;
+    for (int kk = 0; kk < per && kk < 4; ++kk) {
+        const int k = k0 + kk;
+        if (k >= K)
+            break;
+        uint32_t run = 0;
+        for (int s = 0; s < nseg; ++s) {
+            const uint32_t v = segsum[(int64_t)s * K + k];
+            segsum[(int64_t)s * K + k] = run;
+            run += v;
+        }
+        tot[kk] = run;
+        mine += run;
+    }
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    uint32_t inc = v;
+    uint32_t inc = mine;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
         const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
@@ -92,93 +158,40 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* l
             inc += n;
     }
     if (lane == kWave - 1)
-        lds_waves[wave] = inc;
+        sw[wave] = inc;
     __syncthreads();
-    uint32_t off = 0, tot = 0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
-        const uint32_t s = lds_waves[w];
-        off += (w < wave) ? s : 0u;
-        tot += s;
+    uint32_t base = inc - mine, all = 0;
+    for (int w = 0; w < 1024 / kWave; ++w) {
+        base += (w < wave) ? sw[w] : 0u;
+        all += sw[w];
     }
-    __syncthreads();
-    block_total = tot;
-    return off + inc - v;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* table, int K, int64_t B,
-                                                        int64_t M, uint32_t* blocksum)
-{
-    __shared__ uint32_t sw[kWavesPerBlock];
-    const int64_t m0 = (int64_t)blockIdx.x * kScanBlockItems + (int64_t)threadIdx.x * kScanItems;
-    uint32_t s = 0;
-    if (m0 < M) {
-        int64_t k = m0 / B, u = m0 - k * B;
-        for (int j = 0; j < kScanItems && m0 + j < M; ++j) {
-            s += table[u * K + k];
-            if (++u == B) {
-                u = 0;
-                ++k;
-            }
-        }
+    for (int kk = 0; kk < per && kk < 4; ++kk) {
+        const int k = k0 + kk;
+        if (k >= K)
+            break;
+        for (int s = 0; s < nseg; ++s)
+            segsum[(int64_t)s * K + k] += base;
+        base += tot[kk];
     }
-    uint32_t tot;
-    block_exclusive_scan(s, sw, tot);
-    if (threadIdx.x == 0)
-        blocksum[blockIdx.x] = tot;
-}
-
-// One workgroup of 1024 threads: exclusive scan of nb <= 1024 block sums.
-__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* blocksum, int nb, uint32_t* total,
-                                                      DiagDev* diag)
-{
-    __shared__ uint32_t sw[1024 / kWave];
-    const uint32_t v = (threadIdx.x < (unsigned)nb) ? blocksum[threadIdx.x] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(v, sw, tot);
-    if (threadIdx.x < (unsigned)nb)
-        blocksum[threadIdx.x] = ex;
     if (threadIdx.x == 0) {
-        *total = tot;
-        atomicAdd(&diag->accepted, (unsigned long long)tot);
+        *total = all;
+        atomicAdd(&diag->accepted, (unsigned long long)all);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* table, int K, int64_t B, int64_t M,
-                                                      const uint32_t* blocksum)
+__global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int64_t B, int seg,
+                                                     const uint32_t* segsum)
 {
-    __shared__ uint32_t sw[kWavesPerBlock];
-    const int64_t m0 = (int64_t)blockIdx.x * kScanBlockItems + (int64_t)threadIdx.x * kScanItems;
-    uint32_t vals[kScanItems];
-    uint32_t s = 0;
-    int64_t k0 = 0, u0 = 0;
-    if (m0 < M) {
-        k0 = m0 / B;
-        u0 = m0 - k0 * B;
-        int64_t k = k0, u = u0;
-#pragma unroll
-        for (int j = 0; j < kScanItems; ++j) {
-            vals[j] = (m0 + j < M) ? table[u * K + k] : 0u;
-            s += vals[j];
-            if (++u == B) {
-                u = 0;
-                ++k;
-            }
-        }
-    }
-    uint32_t tot;
-    uint32_t run = block_exclusive_scan(s, sw, tot) + blocksum[blockIdx.x];
-    if (m0 < M) {
-        int64_t k = k0, u = u0;
-#pragma unroll
-        for (int j = 0; j < kScanItems; ++j) {
-            if (m0 + j < M)
-                table[u * K + k] = run;
-            run += vals[j];
-            if (++u == B) {
-                u = 0;
-                ++k;
-            }
-        }
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    const int s = blockIdx.y;
+    if (k >= K)
+        return;
+    const int64_t u0 = (int64_t)s * seg, u1 = min(u0 + seg, B);
+    uint32_t run = segsum[(int64_t)s * K + k];
+    for (int64_t u = u0; u < u1; ++u) {
+        const uint32_t c = table[u * K + k];
+        table[u * K + k] = run;
+        run += c;
     }
 }
 
@@ -192,61 +205,68 @@ __global__ __launch_bounds__(kBlock) void k_scatter(EventsDev ev, int W, int H, 
     extern __shared__ uint32_t lds[];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    uint32_t* base = lds + wave * (K + 128);
-    uint32_t* tag = base + K;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t unit = blk * kWavesPerBlock + wave;
+    uint32_t* base = lds + wave * K;
     if (unit < B) {
         const uint32_t* row = table + unit * K;
         for (int k = lane; k < K; k += kWave)
             base[k] = row[k];
     }
-    for (int k = lane; k < 128; k += kWave)
-        tag[k] = 0xFFFFFFFFu;
     __syncthreads();
     if (unit >= B)
         return;  // whole wave leaves together
 
     const uint32_t tmask = (1u << tile_log) - 1u;
+    const int kbits = key_bits_for((uint32_t)K);
     const int64_t t_ref = ev.t[0];
     const int64_t lo = unit << unit_log;
     const int64_t hi = min(lo + ((int64_t)1 << unit_log), ev.n);
     int64_t t_carry = (lo > 0) ? ev.t[lo - 1] : INT64_MIN;
     uint32_t flags = 0;
-    for (int64_t i0 = lo; i0 < hi; i0 += kWave) {
-        const int64_t i = i0 + lane;
-        const bool in = i < hi;
-        uint32_t q = 0;
-        bool ok = false;
-        int64_t t = 0;
-        int pos = 0;
-        if (in) {
-            ok = decode(ev, i, W, H, q);
-            t = ev.t[i];
-            pos = ev.p[i] > 0;
+    for (int64_t b0 = lo; b0 < hi; b0 += kBatch * kWave) {
+        uint32_t xs[kBatch], ys[kBatch];
+        int64_t ts[kBatch];
+        int ps[kBatch];
+#pragma unroll
+        for (int s = 0; s < kBatch; ++s) {
+            // clamped index, no select on the loaded values: all loads of the
+            // batch stay in flight together
+            const int64_t i = min(b0 + s * kWave + lane, hi - 1);
+            xs[s] = ev.x[i];
+            ys[s] = ev.y[i];
+            ts[s] = ev.t[i];
+            ps[s] = ev.p[i];
         }
-        // decreasing time versus the previous event in array order
-        int64_t tprev = __shfl_up(t, 1);
-        if (lane == 0)
-            tprev = t_carry;
-        if (in && t < tprev)
-            flags |= 1u;  // ESI_DIAG_UNSORTED
-        t_carry = __shfl(t, kWave - 1);
-        const int64_t dt = t - t_ref;
-        if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
-            flags |= 4u;  // ESI_DIAG_TIME_RANGE
-        const uint32_t key = q >> tile_log;
-        uint32_t slot;
-        const bool ranked = wave_stable_rank(ok, key, base, tag, slot);
-        if (ok) {
-            if (ranked && (int64_t)slot < cap)
-                records[slot] = pack_record(dt, q & tmask, pos);
-            else
-                flags |= 8u;  // ESI_DIAG_INTERNAL: never expected
+#pragma unroll
+        for (int s = 0; s < kBatch; ++s) {
+            const int64_t i = b0 + s * kWave + lane;
+            const bool in = i < hi;
+            uint32_t q;
+            const bool ok = in && valid_q(xs[s], ys[s], W, H, q);
+            const int64_t t = ts[s];
+            // decreasing time versus the previous event in array order
+            int64_t tprev = __shfl_up(t, 1);
+            if (lane == 0)
+                tprev = t_carry;
+            if (in && t < tprev)
+                flags |= 1u;  // ESI_DIAG_UNSORTED
+            t_carry = __shfl(t, kWave - 1);
+            const int64_t dt = t - t_ref;
+            if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
+                flags |= 4u;  // ESI_DIAG_TIME_RANGE
+            const uint32_t key = ok ? (q >> tile_log) : 0u;
+            const uint32_t slot = wave_stable_rank(ok, key, kbits, base);
+            if (ok) {
+                if ((int64_t)slot < cap)
+                    records[slot] = pack_record(dt, q & tmask, ps[s] > 0);
+                else
+                    flags |= 8u;  // ESI_DIAG_INTERNAL: never expected
+            }
         }
     }
     // one atomic per wave with any flag
-    const uint64_t any = __ballot(flags != 0);
-    if (any) {
+    if (__ballot(flags != 0)) {
         uint32_t f = flags;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1)
@@ -258,24 +278,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter(EventsDev ev, int W, int H, 
 
 }  // namespace
 
+int scan_segment_units(int64_t B)
+{
+    int64_t seg = 64;
+    while ((B + seg - 1) / seg > 64)
+        seg *= 2;
+    return (int)seg;
+}
+
 hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                          const CallScratch& cs, DiagDev* diag, hipStream_t stream)
 {
     const int K = sc.ntiles;
     const int64_t B = sc.nunits;
-    const int64_t M = (int64_t)K * B;
     const unsigned blocks_units = (unsigned)((B + kWavesPerBlock - 1) / kWavesPerBlock);
     const size_t lds_hist = sizeof(uint32_t) * kWavesPerBlock * K;
     hipLaunchKernelGGL(k_hist, dim3(blocks_units), dim3(kBlock), lds_hist, stream, ev, st.W, st.H,
                        sc.tile_log, K, sc.unit_log, B, cs.table, diag);
-    const unsigned nb = (unsigned)((M + kScanBlockItems - 1) / kScanBlockItems);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, cs.table, K, B, M,
+    const int seg = scan_segment_units(B);
+    const int nseg = (int)((B + seg - 1) / seg);
+    const dim3 grid((unsigned)((K + kBlock - 1) / kBlock), (unsigned)nseg);
+    hipLaunchKernelGGL(k_seg_sum, grid, dim3(kBlock), 0, stream, cs.table, K, B, seg, cs.blocksum);
+    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, stream, cs.blocksum, K, nseg, cs.total,
+                       diag);
+    hipLaunchKernelGGL(k_seg_down, grid, dim3(kBlock), 0, stream, cs.table, K, B, seg,
                        cs.blocksum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, cs.blocksum, (int)nb,
-                       cs.total, diag);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, stream, cs.table, K, B, M,
-                       cs.blocksum);
-    const size_t lds_scatter = sizeof(uint32_t) * kWavesPerBlock * (K + 128);
+    const size_t lds_scatter = sizeof(uint32_t) * kWavesPerBlock * K;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_units), dim3(kBlock), lds_scatter, stream, ev, st.W,
                        st.H, sc.tile_log, K, sc.unit_log, B, cs.table, cs.records, ev.n, diag);
     return hipGetLastError();

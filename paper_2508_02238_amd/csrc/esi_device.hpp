@@ -20,31 +20,33 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 // Per-call constants of the method.
 struct MethodParams {
     double C, k, b, s_min, s_max, inv_range;  // inv_range = 1 / (s_max - s_min)
-    int b_kind;                               // 1, 2, 3, 4: integer power; 0: pow()
     int decay_then_add;
     int lazy;
 };
 
+// How d = max(1 - k dt, 0)^b is evaluated: b = 1 and b = 2 exactly by
+// multiplication, any other b by pow().
+enum DecayKind { kDecayB1 = 1, kDecayB2 = 2, kDecayPow = 0 };
+
+__device__ __noinline__ double decay_pow(double u, double b) { return pow(u, b); }
+
+// u^b for u in [0, 1].
+template <int BK>
+__device__ __forceinline__ double power_b(double u, double b)
+{
+    if (BK == kDecayB1)
+        return u;
+    if (BK == kDecayB2)
+        return u * u;
+    return decay_pow(u, b);
+}
+
 // Eq. (4) as a truncated power: d(dt) = max(1 - k dt, 0)^b, dt >= 0 integer us.
+template <int BK>
 __device__ __forceinline__ double decay(const MethodParams& mp, int64_t dt)
 {
     const double u = __fma_rn(-mp.k, (double)dt, 1.0);
-    if (!(u > 0.0))
-        return 0.0;
-    switch (mp.b_kind) {
-    case 1:
-        return u;
-    case 2:
-        return u * u;
-    case 3:
-        return u * u * u;
-    case 4: {
-        const double u2 = u * u;
-        return u2 * u2;
-    }
-    default:
-        return pow(u, mp.b);
-    }
+    return (u > 0.0) ? power_b<BK>(u, mp.b) : 0.0;
 }
 
 __device__ __forceinline__ double clamp_s(const MethodParams& mp, double s)
@@ -53,12 +55,13 @@ __device__ __forceinline__ double clamp_s(const MethodParams& mp, double s)
 }
 
 // One event of Alg. 2 at a pixel whose state is (S, T, N, P).
+template <int BK>
 __device__ __forceinline__ void apply_event(const MethodParams& mp, double& S, int64_t& T,
                                             uint32_t& N, int32_t& P, int64_t t, int pos)
 {
     int64_t dt = t - T;
     dt = dt < 0 ? 0 : dt;
-    const double d = decay(mp, dt);
+    const double d = decay<BK>(mp, dt);
     const double s = pos ? mp.C : -mp.C;
     const double v = mp.decay_then_add ? __fma_rn(S, d, s) : (S + s) * d;
     S = clamp_s(mp, v);
@@ -68,6 +71,7 @@ __device__ __forceinline__ void apply_event(const MethodParams& mp, double& S, i
 }
 
 // Eq. (14) of the state seen at t_f (decayed to t_f unless lazy), in [0, 1].
+template <int BK>
 __device__ __forceinline__ float frame_value(const MethodParams& mp, double S, int64_t T,
                                              int64_t t_f)
 {
@@ -75,7 +79,20 @@ __device__ __forceinline__ float frame_value(const MethodParams& mp, double S, i
     if (!mp.lazy) {
         int64_t dt = t_f - T;
         dt = dt < 0 ? 0 : dt;
-        v = clamp_s(mp, S * decay(mp, dt));
+        v = clamp_s(mp, S * decay<BK>(mp, dt));
+    }
+    return (float)((v - mp.s_min) * mp.inv_range);
+}
+
+// The same value from u = 1 - k (t_f - T) (not clipped), as the frame loop
+// keeps it: d = min(max(u, 0), 1)^b (u > 1 only when t_f < T: dt = 0).
+template <int BK>
+__device__ __forceinline__ float frame_value_u(const MethodParams& mp, double S, double u)
+{
+    double v = S;
+    if (!mp.lazy) {
+        const double uc = fmin(u, 1.0);
+        v = clamp_s(mp, (uc > 0.0) ? S * power_b<BK>(uc, mp.b) : 0.0);
     }
     return (float)((v - mp.s_min) * mp.inv_range);
 }
@@ -103,6 +120,16 @@ __device__ __forceinline__ int record_pos(uint64_t r) { return (int)(r >> 63); }
 
 constexpr int64_t kMaxSpan = (int64_t)1 << 47;
 
+// Read-only data that stays unchanged for the whole kernel, read at a
+// wave-uniform index: through the constant address space the compiler emits
+// scalar loads (a vector load would be waited for with the same counter as
+// the kernel's earlier stores).
+template <typename T>
+__device__ __forceinline__ T load_const(const T* p, int64_t i)
+{
+    return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
 // Ordering point for LDS traffic between the lanes of one wave: the lanes
 // of a wave issue in lockstep and LDS serves a wave's requests in order, so a
 // fence at wavefront scope plus a compiler barrier suffice.
@@ -113,55 +140,39 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // Stable multisplit rank inside one wave step.  Lane l holds an element with
-// key `key` (valid when `ok`); lanes are in array order.  On return, for valid
-// lanes, `pos` = counter[key] (before this step) + number of lower valid lanes
-// with the same key, and counter[key] has been advanced by the number of
-// valid lanes with that key.  `tag` is a 128-entry per-wave LDS array holding
-// 0xFFFFFFFF on entry (and on return).  Leader election: the lowest lane of
-// each hash slot wins an atomic min; lanes whose key differs from their
-// leader's retry in a later round; peers of a leader are found by matching
-// the 6 bits of the leader's lane id with ballots.  Every round completes at
-// least the leader of each slot, so 64 rounds always suffice; the bound also
-// guarantees termination.  Returns false on a lane left unranked (never
-// expected).
-__device__ __forceinline__ bool wave_stable_rank(bool ok, uint32_t key, uint32_t* counter,
-                                                 uint32_t* tag, uint32_t& pos)
+// key `key` < 2^key_bits (valid when `ok`); lanes are in array order.
+// Returns, for valid lanes, counter[key] (before this step) plus the number of
+// lower valid lanes with the same key, and advances counter[key] by the
+// number of valid lanes with that key.  The lanes sharing a key are found by
+// matching the key one bit at a time with ballots (a wave-wide match), so the
+// ranks are stable without atomics.
+__device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, int key_bits,
+                                                     uint32_t* counter)
 {
     const uint32_t lane = __lane_id();
-    const uint32_t slot = key & 127u;
-    uint64_t pending = __ballot(ok);
-    pos = 0;
-    for (int round = 0; pending && round < kWave; ++round) {
-        const bool mine_pending = (pending >> lane) & 1ull;
-        if (mine_pending)
-            atomicMin(&tag[slot], lane);
-        wave_sync();
-        const uint32_t leader = mine_pending ? (tag[slot] & 63u) : lane;
-        const uint32_t lkey = (uint32_t)__shfl((int)key, (int)leader);
-        const bool mine = mine_pending && (lkey == key);
-        uint64_t peers = __ballot(mine);
-#pragma unroll
-        for (int bit = 0; bit < 6; ++bit) {
-            const bool lb = (leader >> bit) & 1u;
-            const uint64_t bm = __ballot(mine && lb);
-            peers &= lb ? bm : ~bm;
-        }
-        const uint64_t below = peers & ((1ull << lane) - 1ull);
-        const uint32_t r = (uint32_t)__popcll(below);
-        const uint32_t c = (uint32_t)__popcll(peers);
-        uint32_t old = 0;
-        if (mine && lane == leader) {
-            old = counter[key];
-            counter[key] = old + c;
-            tag[slot] = 0xFFFFFFFFu;
-        }
-        wave_sync();
-        old = (uint32_t)__shfl((int)old, (int)leader);
-        if (mine)
-            pos = old + r;
-        pending &= ~__ballot(mine);
+    uint64_t peers = __ballot(ok);
+    for (int bit = 0; bit < key_bits; ++bit) {
+        const bool lb = (key >> bit) & 1u;
+        const uint64_t bm = __ballot(lb);
+        peers &= lb ? bm : ~bm;
     }
-    return !((pending >> lane) & 1ull);
+    const uint32_t r = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+    const uint32_t c = (uint32_t)__popcll(peers);
+    const uint32_t base = ok ? counter[key] : 0u;
+    wave_sync();  // every lane has read its counter before the update
+    if (ok && r + 1u == c)
+        counter[key] = base + c;  // the last lane of each key group
+    wave_sync();
+    return base + r;
+}
+
+// Bits needed for keys in [0, n).
+__host__ __device__ inline int key_bits_for(uint32_t n)
+{
+    int b = 0;
+    while (b < 32 && (1u << b) < n)
+        ++b;
+    return b;
 }
 
 }  // namespace esi

@@ -22,9 +22,7 @@ struct Schedule {
 };
 
 constexpr int kMaxTiles = 3840;               // per-wave LDS tables fit in 64 KB
-constexpr int64_t kMaxTable = (int64_t)1 << 22; // K * B entries (scan: 1024 blocks of 4096)
-constexpr int kScanItems = 16;
-constexpr int kScanBlockItems = kBlock * kScanItems;  // 4096
+constexpr int64_t kMaxTable = (int64_t)1 << 22; // K * B entries of the bucketing table
 constexpr int kChunk = 2048;
 
 struct DiagDev {
@@ -37,7 +35,7 @@ struct DiagDev {
 // Scratch of one integrate call (device).
 struct CallScratch {
     uint32_t* table;      // [B][K]: counts, then exclusive offsets in (tile, unit) order
-    uint32_t* blocksum;   // [ceil(K*B / 4096)]
+    uint32_t* blocksum;   // [nseg][K]: per-segment sums, then offsets
     uint32_t* total;      // [1]: number of accepted events
     uint64_t* records;    // [n]
 };
@@ -59,6 +57,9 @@ struct StateDev {
     int W, H;
     int64_t npix;
 };
+
+// Units per segment of the column-wise table scan (at most 64 segments).
+int scan_segment_units(int64_t B);
 
 // Kernel launchers (asynchronous on `stream`; return the launch error).
 hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule& sc,

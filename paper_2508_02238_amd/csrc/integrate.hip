@@ -1,9 +1,9 @@
 // integrate.hip -- per-tile integration of the bucketed events and frames.
 //
 // One workgroup (256 threads) owns a tile of 256 * PPT consecutive pixels;
-// thread `tid` owns pixels tid + 256 i (i < PPT), so that a frame row of the
-// tile is written by the workgroup as contiguous 1 KB pieces.  The pixel
-// state (S, T, N, P) stays in registers for the whole call, in FP64 for S.
+// thread `tid` owns pixels tid + 256 i (i < PPT), so that each wave writes a
+// frame row piece of 256 contiguous bytes per pixel slot.  The pixel state
+// (S, T, N, P) stays in registers for the whole call, S in FP64.
 //
 // The tile's records (array order inside the tile, from the bucketing pass)
 // are consumed in chunks of kChunk:
@@ -12,16 +12,26 @@
 //      an exclusive scan over (pixel, wave) counters, a scatter into LDS, so
 //      each pixel's events of the chunk are contiguous and in array order;
 //   3. every frame j with t_frames[j] earlier than the next chunk's first
-//      event is now complete up to t_frames[j]: each thread applies its
-//      pixels' events with t <= t_frames[j] (Alg. 2 event loop) and writes
-//      the frame value (Eq. (14)); then applies the rest of the chunk.
+//      event is complete after this chunk: for each such frame each thread
+//      applies its pixels' events with t <= t_frames[j] (Alg. 2 event loop)
+//      and writes the frame value (Eq. (14)); then it applies the rest of
+//      the chunk.
 // Frames after the last event are written from the final state.
+//
+// The frame loop index and the frame times are wave-uniform (scalar loads):
+// on CDNA a wait for a vector load also waits for every earlier store, so a
+// per-frame vector load would stall on the previous frame's stores.
+// Between events the decayed snapshot is advanced incrementally:
+// u = 1 - k (t_f - T) drops by k (t_f - t_f') from one frame to the next.
 #include <hip/hip_runtime.h>
 
 #include "esi_internal.hpp"
 
 namespace esi {
 namespace {
+
+// s_waitcnt immediate (gfx9 encoding): vmcnt = 0, expcnt and lgkmcnt not waited.
+constexpr int kWaitVmcnt0 = 0x0F70;
 
 struct FrameOut {
     const int64_t* t_frames;
@@ -30,45 +40,98 @@ struct FrameOut {
     uint8_t* frames_u8;
 };
 
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// First index in [lo, nf) whose frame time is >= t (nf if none); frame times
+// are non-decreasing (otherwise the result is some index in [lo, nf]).
+__device__ __forceinline__ int first_frame_at_or_after(const int64_t* tf, int lo, int nf, int64_t t)
+{
+    int hi = nf;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (load_const(tf, mid) < t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 template <int PPT>
 struct Pixels {
     double S[PPT];
+    double u[PPT];      // 1 - k (t_f - T) at the last frame time written
     int64_t T[PPT];
     uint32_t N[PPT];
     int32_t P[PPT];
+    bool fresh[PPT];    // u is valid (no event since the last frame)
 };
 
-template <int PPT>
-__device__ __forceinline__ void write_frame(const MethodParams& mp, const Pixels<PPT>& px,
-                                            const FrameOut& fo, int j, int64_t q0, int64_t npix,
-                                            int64_t t_f)
+// Frames [j0, j1) with the events of the current chunk interleaved
+// (ptr/end/tn: each pixel's next event in `sorted`).
+template <int PPT, int BK>
+__device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>& px,
+                                            const FrameOut& fo, int j0, int j1, int64_t& tf_prev,
+                                            const uint64_t* sorted, uint32_t* ptr,
+                                            const uint32_t* end, int64_t* tn, int64_t t_ref,
+                                            int64_t q0, int64_t npix)
 {
+    int64_t t_next_f = (j0 < j1) ? load_const(fo.t_frames, j0) : 0;
+    for (int j = j0; j < j1; ++j) {
+        const int64_t t_f = t_next_f;
+        if (j + 1 < j1)
+            t_next_f = load_const(fo.t_frames, j + 1);  // one frame ahead
+        const double dk = mp.k * (double)(t_f - tf_prev);
+        tf_prev = t_f;
+        float F[PPT];
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-        const int64_t q = q0 + (int64_t)i * kBlock;
-        if (q < npix) {
-            const float F = frame_value(mp, px.S[i], px.T[i], t_f);
-            const size_t o = (size_t)j * (size_t)npix + (size_t)q;
-            if (fo.frames)
-                __builtin_nontemporal_store(F, fo.frames + o);
-            if (fo.frames_u8)
-                fo.frames_u8[o] = frame_code(F);
+        for (int i = 0; i < PPT; ++i) {
+            while (ptr[i] < end[i] && tn[i] <= t_f) {
+                const uint64_t r = sorted[ptr[i]];
+                apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], tn[i], record_pos(r));
+                px.fresh[i] = false;
+                ++ptr[i];
+                tn[i] = (ptr[i] < end[i]) ? t_ref + record_dt(sorted[ptr[i]]) : INT64_MAX;
+            }
+            if (px.fresh[i]) {
+                px.u[i] -= dk;
+            } else {
+                px.u[i] = __fma_rn(-mp.k, (double)(t_f - px.T[i]), 1.0);
+                px.fresh[i] = true;
+            }
+            F[i] = frame_value_u<BK>(mp, px.S[i], px.u[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int64_t q = q0 + (int64_t)i * kBlock;
+            if (q < npix) {
+                const size_t o = (size_t)j * (size_t)npix + (size_t)q;
+                if (fo.frames)
+                    __builtin_nontemporal_store(F[i], fo.frames + o);
+                if (fo.frames_u8)
+                    fo.frames_u8[o] = frame_code(F[i]);
+            }
         }
     }
 }
 
-template <int PPT>
+template <int PPT, int BK>
 __global__ __launch_bounds__(kBlock) void k_integrate(
     const uint64_t* __restrict__ records, const uint32_t* __restrict__ table,
-    const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t, int K, int tile_log,
-    StateDev st, MethodParams mp, FrameOut fo, DiagDev* diag)
+    const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t, int K, StateDev st,
+    MethodParams mp, FrameOut fo, DiagDev* diag)
 {
     constexpr int TILE = kBlock * PPT;
     constexpr int PER_WAVE = kChunk / kWavesPerBlock;     // records per wave per chunk
     constexpr int STEPS = PER_WAVE / kWave;               // records per lane per chunk
     __shared__ uint64_t sorted[kChunk];
     __shared__ uint32_t cnt[kWavesPerBlock][TILE];
-    __shared__ uint32_t tag[kWavesPerBlock][128];
     __shared__ uint32_t scan_w[kWavesPerBlock];
 
     const int tid = threadIdx.x;
@@ -77,58 +140,69 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
     const int tile = blockIdx.x;
     const int64_t q0 = (int64_t)tile * TILE + tid;
     const int64_t npix = st.npix;
+    const int kbits = key_bits_for((uint32_t)TILE);
 
     Pixels<PPT> px;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int64_t q = q0 + (int64_t)i * kBlock;
-        if (q < npix) {
-            px.S[i] = (double)st.S_hi[q] + (double)st.S_lo[q];
-            px.T[i] = st.T[q];
-            px.N[i] = st.N[q];
-            px.P[i] = st.P[q];
-        } else {
-            px.S[i] = 0.0;
-            px.T[i] = 0;
-            px.N[i] = 0;
-            px.P[i] = 0;
-        }
+        const bool in = q < npix;
+        px.S[i] = in ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
+        px.T[i] = in ? st.T[q] : 0;
+        px.N[i] = in ? st.N[q] : 0u;
+        px.P[i] = in ? st.P[q] : 0;
+        px.u[i] = 1.0;
+        px.fresh[i] = false;
     }
 
+    // the tile's records [rs, re); read-only here, so scalar loads
     uint32_t rs = 0, re = 0;
     int64_t t_ref = 0;
     if (table) {
-        rs = table[tile];
-        re = (tile + 1 < K) ? table[tile + 1] : *total;
-        t_ref = ev_t[0];
+        rs = load_const(table, tile);
+        re = (tile + 1 < K) ? load_const(table, tile + 1) : load_const(total, 0);
+        t_ref = load_const(ev_t, 0);
     }
-    for (int k = lane; k < 128; k += kWave)
-        tag[wave][k] = 0xFFFFFFFFu;
 
-    int j = 0;  // next frame to write
+    int j = 0;               // next frame to write (uniform)
+    int64_t tf_prev = 0;     // time of the last frame written (uniform)
     bool bad = false;
+    uint32_t ptr[PPT], end[PPT];
+    int64_t tn[PPT];
+
+    // Records of a chunk, this wave's quarter, step-major (array order).
+    // Clamped indices: no select on loaded values, all loads stay in flight.
+    uint64_t rr[STEPS], rr_next[STEPS];
+    if (rs < re) {
+        const int cn0 = (int)(min(rs + (uint32_t)kChunk, re) - rs);
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s)
+            rr[s] = records[rs + min(wave * PER_WAVE + s * kWave + lane, cn0 - 1)];
+    }
+    // nothing may be pending on `rr` at the loop head, or the compiler waits
+    // there for everything outstanding, frame stores included
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     for (uint32_t cs = rs; cs < re; cs += kChunk) {
         const uint32_t ce = min(cs + (uint32_t)kChunk, re);
         const int cn = (int)(ce - cs);
-        const int64_t t_next = (ce < re) ? t_ref + record_dt(records[ce]) : INT64_MAX;
+        const int64_t t_next = (ce < re) ? t_ref + record_dt(load_const(records, ce)) : INT64_MAX;
+        // prefetch the next chunk before this chunk's frame stores are issued
+        if (ce < re) {
+            const int cn1 = (int)(min(ce + (uint32_t)kChunk, re) - ce);
+#pragma unroll
+            for (int s = 0; s < STEPS; ++s)
+                rr_next[s] = records[ce + min(wave * PER_WAVE + s * kWave + lane, cn1 - 1)];
+        }
 
-        // 1. this wave's quarter of the chunk, in array order (step-major)
-        uint64_t rr[STEPS];
+        // 2a. stable ranks inside the wave
+        for (int k = lane; k < TILE; k += kWave)
+            cnt[wave][k] = 0;
+        wave_sync();
         uint32_t rank[STEPS];
 #pragma unroll
         for (int s = 0; s < STEPS; ++s) {
             const int c = wave * PER_WAVE + s * kWave + lane;
-            rr[s] = (c < cn) ? records[cs + c] : 0ull;
-        }
-        for (int k = lane; k < TILE; k += kWave)
-            cnt[wave][k] = 0;
-        wave_sync();
-        // 2a. stable ranks inside the wave
-        bool ranked = true;
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            const int c = wave * PER_WAVE + s * kWave + lane;
-            ranked &= wave_stable_rank(c < cn, record_lpx(rr[s]), cnt[wave], tag[wave], rank[s]);
+            rank[s] = wave_stable_rank(c < cn, (record_lpx(rr[s]) & (TILE - 1)), kbits, cnt[wave]);
         }
         __syncthreads();
         // 2b. exclusive scan over (pixel, wave), pixel-major
@@ -170,8 +244,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         for (int s = 0; s < STEPS; ++s) {
             const int c = wave * PER_WAVE + s * kWave + lane;
             if (c < cn) {
-                const uint32_t at = cnt[wave][record_lpx(rr[s])] + rank[s];
-                if (ranked && at < (uint32_t)cn)
+                const uint32_t at = cnt[wave][(record_lpx(rr[s]) & (TILE - 1))] + rank[s];
+                if (at < (uint32_t)cn)
                     sorted[at] = rr[s];
                 else
                     bad = true;
@@ -179,9 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         }
         __syncthreads();
 
-        // 3. walk frames and events
-        uint32_t ptr[PPT], end[PPT];
-        int64_t tn[PPT];
+        // 3. frames that this chunk completes, with its events interleaved
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             const int l = tid + i * kBlock;
@@ -189,34 +261,40 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
             ptr[i] = min(cnt[0][l], end[i]);
             tn[i] = (ptr[i] < end[i]) ? t_ref + record_dt(sorted[ptr[i]]) : INT64_MAX;
         }
-        for (; j < fo.nf; ++j) {
-            const int64_t t_f = fo.t_frames[j];
-            if (t_f >= t_next)
-                break;
-#pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                while (ptr[i] < end[i] && tn[i] <= t_f) {
-                    const uint64_t r = sorted[ptr[i]];
-                    apply_event(mp, px.S[i], px.T[i], px.N[i], px.P[i], tn[i], record_pos(r));
-                    ++ptr[i];
-                    tn[i] = (ptr[i] < end[i]) ? t_ref + record_dt(sorted[ptr[i]]) : INT64_MAX;
-                }
-            }
-            write_frame<PPT>(mp, px, fo, j, q0, npix, t_f);
-        }
+        const int j_end = (t_next == INT64_MAX)
+                              ? fo.nf
+                              : first_frame_at_or_after(fo.t_frames, j, fo.nf, t_next);
+        // Wait for the prefetched records now: this also drains the frame
+        // stores of the previous chunk (one counter covers loads and stores),
+        // which have had the whole sort to complete.  Waiting after this
+        // chunk's stores instead would stall on all of them.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        walk_frames<PPT, BK>(mp, px, fo, j, j_end, tf_prev, sorted, ptr, end, tn, t_ref, q0,
+                             npix);
+        j = j_end;
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             while (ptr[i] < end[i]) {
                 const uint64_t r = sorted[ptr[i]];
-                apply_event(mp, px.S[i], px.T[i], px.N[i], px.P[i], t_ref + record_dt(r),
-                            record_pos(r));
+                apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t_ref + record_dt(r),
+                                record_pos(r));
+                px.fresh[i] = false;
                 ++ptr[i];
             }
         }
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s)
+            rr[s] = rr_next[s];
         __syncthreads();  // LDS is reused by the next chunk
     }
-    for (; j < fo.nf; ++j)
-        write_frame<PPT>(mp, px, fo, j, q0, npix, fo.t_frames[j]);
+    // frames after the last event
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        ptr[i] = 0;
+        end[i] = 0;
+        tn[i] = INT64_MAX;
+    }
+    walk_frames<PPT, BK>(mp, px, fo, j, fo.nf, tf_prev, sorted, ptr, end, tn, t_ref, q0, npix);
 
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
@@ -234,14 +312,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         atomicOr(&diag->flags, 8u);  // ESI_DIAG_INTERNAL: never expected
     // frame times must be non-decreasing; the first workgroup checks
     if (tile == 0) {
-        bool bad = false;
+        bool unsorted = false;
         for (int jj = 1 + tid; jj < fo.nf; jj += kBlock)
-            bad |= fo.t_frames[jj] < fo.t_frames[jj - 1];
-        if (bad)
+            unsorted |= fo.t_frames[jj] < fo.t_frames[jj - 1];
+        if (unsorted)
             atomicOr(&diag->flags, 2u);  // ESI_DIAG_FRAMES_UNSORTED
     }
 }
 
+template <int BK>
 __global__ __launch_bounds__(kBlock) void k_snapshot(StateDev st, MethodParams mp, int64_t t_f,
                                                      float* frame, uint8_t* u8)
 {
@@ -249,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(StateDev st, MethodParams m
     if (q >= st.npix)
         return;
     const double S = (double)st.S_hi[q] + (double)st.S_lo[q];
-    const float F = frame_value(mp, S, st.T[q], t_f);
+    const float F = frame_value<BK>(mp, S, st.T[q], t_f);
     if (frame)
         frame[q] = F;
     if (u8)
@@ -273,7 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_reset(StateDev st, int64_t t0, DiagD
     }
 }
 
-template <int PPT>
+int decay_kind(double b) { return b == 1.0 ? kDecayB1 : (b == 2.0 ? kDecayB2 : kDecayPow); }
+
+template <int PPT, int BK>
 hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                               const CallScratch& cs, const MethodParams& mp,
                               const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
@@ -281,11 +362,29 @@ hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Sch
 {
     FrameOut fo{t_frames, nf, frames, frames_u8};
     const bool has = ev.n > 0;
-    hipLaunchKernelGGL(k_integrate<PPT>, dim3(sc.ntiles), dim3(kBlock), 0, stream,
+    hipLaunchKernelGGL((k_integrate<PPT, BK>), dim3(sc.ntiles), dim3(kBlock), 0, stream,
                        has ? cs.records : nullptr, has ? cs.table : nullptr,
-                       has ? cs.total : nullptr, has ? ev.t : nullptr, sc.ntiles, sc.tile_log, st,
-                       mp, fo, diag);
+                       has ? cs.total : nullptr, has ? ev.t : nullptr, sc.ntiles, st, mp, fo, diag);
     return hipGetLastError();
+}
+
+template <int PPT>
+hipError_t launch_integrate_p(const EventsDev& ev, const StateDev& st, const Schedule& sc,
+                              const CallScratch& cs, const MethodParams& mp,
+                              const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
+                              DiagDev* diag, hipStream_t stream)
+{
+    switch (decay_kind(mp.b)) {
+    case kDecayB1:
+        return launch_integrate_t<PPT, kDecayB1>(ev, st, sc, cs, mp, t_frames, nf, frames,
+                                                 frames_u8, diag, stream);
+    case kDecayB2:
+        return launch_integrate_t<PPT, kDecayB2>(ev, st, sc, cs, mp, t_frames, nf, frames,
+                                                 frames_u8, diag, stream);
+    default:
+        return launch_integrate_t<PPT, kDecayPow>(ev, st, sc, cs, mp, t_frames, nf, frames,
+                                                  frames_u8, diag, stream);
+    }
 }
 
 }  // namespace
@@ -297,13 +396,13 @@ hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Sched
 {
     switch (sc.ppt) {
     case 1:
-        return launch_integrate_t<1>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
+        return launch_integrate_p<1>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
     case 2:
-        return launch_integrate_t<2>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
+        return launch_integrate_p<2>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
     case 4:
-        return launch_integrate_t<4>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
+        return launch_integrate_p<4>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
     case 8:
-        return launch_integrate_t<8>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
+        return launch_integrate_p<8>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
     default:
         return hipErrorInvalidValue;
     }
@@ -313,7 +412,19 @@ hipError_t launch_snapshot(const StateDev& st, const MethodParams& mp, int64_t t
                            uint8_t* u8, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((st.npix + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_snapshot, dim3(blocks), dim3(kBlock), 0, stream, st, mp, t_f, frame, u8);
+    switch (decay_kind(mp.b)) {
+    case kDecayB1:
+        hipLaunchKernelGGL(k_snapshot<kDecayB1>, dim3(blocks), dim3(kBlock), 0, stream, st, mp,
+                           t_f, frame, u8);
+        break;
+    case kDecayB2:
+        hipLaunchKernelGGL(k_snapshot<kDecayB2>, dim3(blocks), dim3(kBlock), 0, stream, st, mp,
+                           t_f, frame, u8);
+        break;
+    default:
+        hipLaunchKernelGGL(k_snapshot<kDecayPow>, dim3(blocks), dim3(kBlock), 0, stream, st, mp,
+                           t_f, frame, u8);
+    }
     return hipGetLastError();
 }
 

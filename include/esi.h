@@ -116,7 +116,7 @@ typedef struct {
 typedef struct esi_state esi_state;
 
 /* Create a state for a W x H sensor: S = 0, T = t0_us, N = P = 0 (Alg. 1/2
- * initialisation).  1 <= W, H <= 65535 and W*H <= 7864320 (e.g. 3840 x 2048).
+ * initialisation).  1 <= W, H <= 65535 and W*H <= 4096000 (e.g. 2560 x 1600).
  * The state lives on the current HIP device.  On success *out receives the
  * state; the initialisation is enqueued on `stream`. */
 esi_status esi_create_state(int32_t width, int32_t height, const esi_params *params,

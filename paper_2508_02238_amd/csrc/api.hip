@@ -37,7 +37,7 @@ namespace {
 
 constexpr uint64_t kMagic = 0x3130495345ull;  // "ESI01"
 constexpr uint32_t kProfMax = 1024;
-constexpr int64_t kMaxPixels = (int64_t)kMaxTiles * 256 * 8;
+constexpr int64_t kMaxPixels = (int64_t)kMaxTiles * 256 * 8;  // 4096000
 
 struct SerialHeader {
     uint64_t magic;
@@ -68,29 +68,22 @@ MethodParams method_params(const esi_params& p)
     return mp;
 }
 
-// The split of one call into tiles and bucketing units.  Pick the smallest
-// tile (most workgroups) whose (tile x unit) table stays within kMaxTable
-// entries while still giving at least 2048 bucketing waves.
+// The split of one call into tiles and bucketing units: the smallest tile
+// (most workgroups) with at most kMaxTiles tiles; units of 2^kUnitLog events.
 Schedule make_schedule(int64_t npix, int64_t n)
 {
-    Schedule best{};
+    Schedule s{};
     for (int ppt = 1; ppt <= 8; ppt *= 2) {
-        Schedule s{};
         s.ppt = ppt;
         s.tile_log = 8 + (ppt == 1 ? 0 : ppt == 2 ? 1 : ppt == 4 ? 2 : 3);
         s.ntiles = (int)((npix + (256 * ppt) - 1) / (256 * ppt));
-        s.chunk = kChunk;
-        if (s.ntiles > kMaxTiles)
-            continue;
-        s.unit_log = 10;
-        while (((n + ((int64_t)1 << s.unit_log) - 1) >> s.unit_log) * s.ntiles > kMaxTable)
-            ++s.unit_log;
-        s.nunits = (n + ((int64_t)1 << s.unit_log) - 1) >> s.unit_log;
-        best = s;
-        if (s.nunits >= 2048 || (n >> 10) < 2048)
+        if (s.ntiles <= kMaxTiles)
             break;
     }
-    return best;
+    s.chunk = kChunk;
+    s.unit_log = kUnitLog;
+    s.nunits = (n + ((int64_t)1 << kUnitLog) - 1) >> kUnitLog;
+    return s;
 }
 
 struct DeviceGuard {

@@ -6,24 +6,27 @@
 // consecutive pixels) while keeping array order inside every tile (and so
 // inside every pixel): a counting sort whose ranks are stable.
 //
-//   k_hist      one wave per unit of 2^unit_log consecutive events: per-tile
-//               counts of the unit's valid events -> table[unit][tile];
+//   k_hist      one workgroup per unit of 2^unit_log consecutive events:
+//               per-tile counts of the unit's valid events -> table[unit][tile];
 //               out-of-range events are counted as dropped.
 //   k_seg_sum,  exclusive scan of the table in (tile, unit) order, done
 //   k_seg_scan, column-wise so every access is a coalesced row access:
 //   k_seg_down  per-tile sums over segments of units, a scan over segments
 //               and tiles, then a rescan of each segment writing offsets.
-//   k_scatter   one wave per unit again: walks its events 64 at a time in
-//               order (8 steps loaded ahead), ranks each event stably among
-//               the same-tile events of the unit, writes a 64-bit record
-//               (time offset, pixel in tile, polarity) to its slot.  Also
-//               flags decreasing times and calls whose span the record cannot
-//               hold.
+//   k_bucket    one workgroup per unit again: each wave ranks its quarter of
+//               the unit stably by tile (wave-wide key match), a scan over
+//               (tile, wave) gives every event its place in the unit sorted
+//               by tile, the 64-bit records (time offset, pixel in tile,
+//               polarity) are staged in LDS in that order, and each tile's run
+//               is then written to its bucket in one burst.  Also flags
+//               decreasing times and calls whose span the record cannot hold.
 //
 // Workgroups are dispatched round-robin over the 8 XCDs; units are assigned
 // so that the workgroups of one XCD take consecutive units.  Consecutive
-// units write adjacent pieces of every tile bucket, so a cache line of a
-// bucket is completed inside one XCD's L2 before it is written back.
+// units write adjacent runs of every tile bucket within a short time, so the
+// cache lines of a bucket are completed in one XCD's L2 before they are
+// written back (scattered 8-byte stores spread over the whole kernel would
+// reach HBM as partial lines).
 #include <hip/hip_runtime.h>
 
 #include "esi_internal.hpp"
@@ -32,7 +35,6 @@ namespace esi {
 namespace {
 
 constexpr int kXcds = 8;
-constexpr int kBatch = 8;  // scatter: steps of 64 events loaded ahead
 
 // Bijection blockIdx -> work index that gives each XCD a contiguous range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
@@ -52,57 +54,49 @@ __global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int
                                                  int unit_log, int64_t B, uint32_t* table,
                                                  DiagDev* diag)
 {
-    extern __shared__ uint32_t lds[];
-    const int wave = threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t unit = blk * kWavesPerBlock + wave;
-    uint32_t* h = lds + wave * K;
-    for (int k = lane; k < K; k += kWave)
+    extern __shared__ uint32_t h[];
+    const int64_t unit = xcd_block(blockIdx.x, gridDim.x);
+    for (int k = threadIdx.x; k < K; k += kBlock)
         h[k] = 0;
     __syncthreads();
     uint32_t drop = 0;
-    if (unit < B) {
-        const int64_t lo = unit << unit_log;
-        const int64_t hi = min(lo + ((int64_t)1 << unit_log), ev.n);
-        const bool vec = (((uintptr_t)ev.x | (uintptr_t)ev.y) & 15u) == 0;
-        int64_t i = lo;
-        if (vec) {
-            // 8 events per lane per step: 16-byte loads of x and y
-            for (; i + 8 * kWave <= hi; i += 8 * kWave) {
-                const int64_t e = i + 8 * lane;
-                const uint4 xv = *(const uint4*)(ev.x + e);
-                const uint4 yv = *(const uint4*)(ev.y + e);
-                const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
-                const uint32_t ys[4] = {yv.x, yv.y, yv.z, yv.w};
+    const int64_t lo = unit << unit_log;
+    const int64_t hi = min(lo + ((int64_t)1 << unit_log), ev.n);
+    const bool vec = (((uintptr_t)ev.x | (uintptr_t)ev.y) & 15u) == 0;
+    int64_t i = lo;
+    if (vec) {
+        // 8 events per thread per step: 16-byte loads of x and y
+        for (; i + 8 * kBlock <= hi; i += 8 * kBlock) {
+            const int64_t e = i + 8 * threadIdx.x;
+            const uint4 xv = *(const uint4*)(ev.x + e);
+            const uint4 yv = *(const uint4*)(ev.y + e);
+            const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
+            const uint32_t ys[4] = {yv.x, yv.y, yv.z, yv.w};
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    uint32_t q;
-                    if (valid_q(xs[m] & 0xFFFFu, ys[m] & 0xFFFFu, W, H, q))
-                        atomicAdd(&h[q >> tile_log], 1u);
-                    else
-                        ++drop;
-                    if (valid_q(xs[m] >> 16, ys[m] >> 16, W, H, q))
-                        atomicAdd(&h[q >> tile_log], 1u);
-                    else
-                        ++drop;
-                }
+            for (int m = 0; m < 4; ++m) {
+                uint32_t q;
+                if (valid_q(xs[m] & 0xFFFFu, ys[m] & 0xFFFFu, W, H, q))
+                    atomicAdd(&h[q >> tile_log], 1u);
+                else
+                    ++drop;
+                if (valid_q(xs[m] >> 16, ys[m] >> 16, W, H, q))
+                    atomicAdd(&h[q >> tile_log], 1u);
+                else
+                    ++drop;
             }
         }
-        for (int64_t e = i + lane; e < hi; e += kWave) {
-            uint32_t q;
-            if (valid_q(ev.x[e], ev.y[e], W, H, q))
-                atomicAdd(&h[q >> tile_log], 1u);
-            else
-                ++drop;
-        }
+    }
+    for (int64_t e = i + threadIdx.x; e < hi; e += kBlock) {
+        uint32_t q;
+        if (valid_q(ev.x[e], ev.y[e], W, H, q))
+            atomicAdd(&h[q >> tile_log], 1u);
+        else
+            ++drop;
     }
     __syncthreads();
-    if (unit < B) {
-        uint32_t* row = table + unit * K;
-        for (int k = lane; k < K; k += kWave)
-            row[k] = h[k];
-    }
+    uint32_t* row = table + unit * K;
+    for (int k = threadIdx.x; k < K; k += kBlock)
+        row[k] = h[k];
     if (drop)
         atomicAdd(&diag->dropped, (unsigned long long)drop);
 }
@@ -195,52 +189,63 @@ __global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int
     }
 }
 
-// ---- stable scatter ----------------------------------------------------------
+// ---- stable bucketing, staged in LDS ------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_scatter(EventsDev ev, int W, int H, int tile_log,
-                                                    int K, int unit_log, int64_t B,
-                                                    const uint32_t* table, uint64_t* records,
-                                                    int64_t cap, DiagDev* diag)
+template <int UNIT_LOG>
+__global__ __launch_bounds__(kBlock) void k_bucket(EventsDev ev, int W, int H, int tile_log,
+                                                   int K, int64_t B, const uint32_t* table,
+                                                   uint64_t* records, int64_t cap, DiagDev* diag)
 {
-    extern __shared__ uint32_t lds[];
-    const int wave = threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t unit = blk * kWavesPerBlock + wave;
-    uint32_t* base = lds + wave * K;
-    if (unit < B) {
-        const uint32_t* row = table + unit * K;
-        for (int k = lane; k < K; k += kWave)
-            base[k] = row[k];
-    }
+    constexpr int U = 1 << UNIT_LOG;              // events per unit (workgroup)
+    constexpr int PER_WAVE = U / kWavesPerBlock;  // events per wave
+    constexpr int STEPS = PER_WAVE / kWave;       // steps of 64 per wave
+    constexpr int BATCH = 8;                      // steps loaded ahead
+    static_assert(STEPS % BATCH == 0, "unit size");
+    extern __shared__ uint64_t smem[];
+    uint64_t* staged = smem;                                   // [U]
+    uint32_t* gbase = (uint32_t*)(staged + U);                 // [K] bucket offset of this unit
+    uint16_t* cw = (uint16_t*)(gbase + K);                     // [4][K] per-wave counters
+    uint16_t* skey = cw + kWavesPerBlock * K;                  // [U] tile of each staged record
+
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int lane = tid % kWave;
+    const int64_t unit = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t* row = table + unit * K;
+    for (int k = tid; k < K; k += kBlock)
+        gbase[k] = row[k];
+    for (int k = tid; k < kWavesPerBlock * K; k += kBlock)
+        cw[k] = 0;
     __syncthreads();
-    if (unit >= B)
-        return;  // whole wave leaves together
 
     const uint32_t tmask = (1u << tile_log) - 1u;
     const int kbits = key_bits_for((uint32_t)K);
     const int64_t t_ref = ev.t[0];
-    const int64_t lo = unit << unit_log;
-    const int64_t hi = min(lo + ((int64_t)1 << unit_log), ev.n);
-    int64_t t_carry = (lo > 0) ? ev.t[lo - 1] : INT64_MIN;
+    const int64_t lo = (unit << UNIT_LOG) + (int64_t)wave * PER_WAVE;
+    const int64_t hi = min((unit << UNIT_LOG) + U, ev.n);
+    int64_t t_carry = (lo > 0 && lo - 1 < ev.n) ? ev.t[lo - 1] : INT64_MIN;
     uint32_t flags = 0;
-    for (int64_t b0 = lo; b0 < hi; b0 += kBatch * kWave) {
-        uint32_t xs[kBatch], ys[kBatch];
-        int64_t ts[kBatch];
-        int ps[kBatch];
+    uint64_t recs[STEPS];
+    uint32_t packed[STEPS];  // rank | tile << 16, or ~0 for no event
+    uint16_t* mycw = cw + wave * K;
 #pragma unroll
-        for (int s = 0; s < kBatch; ++s) {
+    for (int b0 = 0; b0 < STEPS; b0 += BATCH) {
+        uint32_t xs[BATCH], ys[BATCH];
+        int64_t ts[BATCH];
+        int ps[BATCH];
+#pragma unroll
+        for (int s = 0; s < BATCH; ++s) {
             // clamped index, no select on the loaded values: all loads of the
             // batch stay in flight together
-            const int64_t i = min(b0 + s * kWave + lane, hi - 1);
+            const int64_t i = max(min(lo + (b0 + s) * kWave + lane, hi - 1), (int64_t)0);
             xs[s] = ev.x[i];
             ys[s] = ev.y[i];
             ts[s] = ev.t[i];
             ps[s] = ev.p[i];
         }
 #pragma unroll
-        for (int s = 0; s < kBatch; ++s) {
-            const int64_t i = b0 + s * kWave + lane;
+        for (int s = 0; s < BATCH; ++s) {
+            const int64_t i = lo + (b0 + s) * kWave + lane;
             const bool in = i < hi;
             uint32_t q;
             const bool ok = in && valid_q(xs[s], ys[s], W, H, q);
@@ -256,16 +261,84 @@ __global__ __launch_bounds__(kBlock) void k_scatter(EventsDev ev, int W, int H, 
             if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
                 flags |= 4u;  // ESI_DIAG_TIME_RANGE
             const uint32_t key = ok ? (q >> tile_log) : 0u;
-            const uint32_t slot = wave_stable_rank(ok, key, kbits, base);
-            if (ok) {
-                if ((int64_t)slot < cap)
-                    records[slot] = pack_record(dt, q & tmask, ps[s] > 0);
-                else
-                    flags |= 8u;  // ESI_DIAG_INTERNAL: never expected
+            const uint32_t rank = wave_stable_rank(ok, key, kbits, mycw);
+            packed[b0 + s] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
+            recs[b0 + s] = pack_record(dt, q & tmask, ps[s] > 0);
+        }
+    }
+    __syncthreads();
+
+    // exclusive scan over (tile, wave), tile-major: start of each wave's run
+    // of each tile inside the unit sorted by tile
+    __shared__ uint32_t scan_w[kWavesPerBlock];
+    __shared__ uint32_t unit_total;
+    {
+        const int kpt = (K + kBlock - 1) / kBlock;  // tiles per thread, consecutive
+        const int k0 = tid * kpt;
+        uint32_t sum = 0;
+        for (int kk = 0; kk < kpt; ++kk) {
+            const int k = k0 + kk;
+            if (k < K)
+                for (int w = 0; w < kWavesPerBlock; ++w)
+                    sum += cw[w * K + k];
+        }
+        uint32_t inc = sum;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
+            if (lane >= o)
+                inc += n;
+        }
+        if (lane == kWave - 1)
+            scan_w[wave] = inc;
+        __syncthreads();
+        uint32_t run = inc - sum;
+        for (int w = 0; w < wave; ++w)
+            run += scan_w[w];
+        if (tid == kBlock - 1)
+            unit_total = run + sum;
+        for (int kk = 0; kk < kpt; ++kk) {
+            const int k = k0 + kk;
+            if (k < K)
+                for (int w = 0; w < kWavesPerBlock; ++w) {
+                    const uint32_t c = cw[w * K + k];
+                    cw[w * K + k] = (uint16_t)run;
+                    run += c;
+                }
+        }
+    }
+    __syncthreads();
+
+    // stage the records in tile order
+    bool bad = false;
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+        if (packed[s] != 0xFFFFFFFFu) {
+            const uint32_t key = packed[s] >> 16;
+            const uint32_t pos = (uint32_t)mycw[key] + (packed[s] & 0xFFFFu);
+            if (pos < (uint32_t)U) {
+                staged[pos] = recs[s];
+                skey[pos] = (uint16_t)key;
+            } else {
+                bad = true;
             }
         }
     }
-    // one atomic per wave with any flag
+    __syncthreads();
+
+    // each tile's run of this unit goes to its bucket: consecutive staged
+    // records of one tile land on consecutive addresses
+    const uint32_t total = min(unit_total, (uint32_t)U);
+    for (uint32_t p = tid; p < total; p += kBlock) {
+        const uint32_t k = skey[p];
+        const int64_t g = (int64_t)gbase[k] + (int64_t)(p - cw[k]);
+        if (k < (uint32_t)K && g >= 0 && g < cap)
+            records[g] = staged[p];
+        else
+            bad = true;
+    }
+    if (bad)
+        flags |= 8u;  // ESI_DIAG_INTERNAL: never expected
     if (__ballot(flags != 0)) {
         uint32_t f = flags;
 #pragma unroll
@@ -286,14 +359,19 @@ int scan_segment_units(int64_t B)
     return (int)seg;
 }
 
+size_t bucket_lds_bytes(int K)
+{
+    return sizeof(uint64_t) * ((size_t)1 << kUnitLog) + sizeof(uint32_t) * K +
+           sizeof(uint16_t) * (kWavesPerBlock * K + ((size_t)1 << kUnitLog));
+}
+
 hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                          const CallScratch& cs, DiagDev* diag, hipStream_t stream)
 {
     const int K = sc.ntiles;
     const int64_t B = sc.nunits;
-    const unsigned blocks_units = (unsigned)((B + kWavesPerBlock - 1) / kWavesPerBlock);
-    const size_t lds_hist = sizeof(uint32_t) * kWavesPerBlock * K;
-    hipLaunchKernelGGL(k_hist, dim3(blocks_units), dim3(kBlock), lds_hist, stream, ev, st.W, st.H,
+    const size_t lds_hist = sizeof(uint32_t) * K;
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)B), dim3(kBlock), lds_hist, stream, ev, st.W, st.H,
                        sc.tile_log, K, sc.unit_log, B, cs.table, diag);
     const int seg = scan_segment_units(B);
     const int nseg = (int)((B + seg - 1) / seg);
@@ -303,9 +381,9 @@ hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule
                        diag);
     hipLaunchKernelGGL(k_seg_down, grid, dim3(kBlock), 0, stream, cs.table, K, B, seg,
                        cs.blocksum);
-    const size_t lds_scatter = sizeof(uint32_t) * kWavesPerBlock * K;
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_units), dim3(kBlock), lds_scatter, stream, ev, st.W,
-                       st.H, sc.tile_log, K, sc.unit_log, B, cs.table, cs.records, ev.n, diag);
+    hipLaunchKernelGGL(k_bucket<kUnitLog>, dim3((unsigned)B), dim3(kBlock), bucket_lds_bytes(K),
+                       stream, ev, st.W, st.H, sc.tile_log, K, B, cs.table, cs.records, ev.n,
+                       diag);
     return hipGetLastError();
 }
 

@@ -146,8 +146,9 @@ __device__ __forceinline__ void wave_sync()
 // number of valid lanes with that key.  The lanes sharing a key are found by
 // matching the key one bit at a time with ballots (a wave-wide match), so the
 // ranks are stable without atomics.
+template <typename CounterT>
 __device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, int key_bits,
-                                                     uint32_t* counter)
+                                                     CounterT* counter)
 {
     const uint32_t lane = __lane_id();
     uint64_t peers = __ballot(ok);
@@ -158,10 +159,10 @@ __device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, int 
     }
     const uint32_t r = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
     const uint32_t c = (uint32_t)__popcll(peers);
-    const uint32_t base = ok ? counter[key] : 0u;
+    const uint32_t base = ok ? (uint32_t)counter[key] : 0u;
     wave_sync();  // every lane has read its counter before the update
     if (ok && r + 1u == c)
-        counter[key] = base + c;  // the last lane of each key group
+        counter[key] = (CounterT)(base + c);  // the last lane of each key group
     wave_sync();
     return base + r;
 }

@@ -11,7 +11,7 @@ namespace esi {
 // How one integrate call is split into work.
 //   tile   = 256 * ppt consecutive pixels (row-major q), one workgroup each in
 //            the integration kernel;
-//   unit   = 2^unit_log consecutive events, one wave each when bucketing.
+//   unit   = 2^unit_log consecutive events, one workgroup each when bucketing.
 struct Schedule {
     int ppt;          // pixels per thread in the integration kernel: 1, 2, 4, 8
     int tile_log;     // log2(256 * ppt)
@@ -21,8 +21,8 @@ struct Schedule {
     int chunk;        // records staged in LDS at a time by the integration kernel
 };
 
-constexpr int kMaxTiles = 3840;               // per-wave LDS tables fit in 64 KB
-constexpr int64_t kMaxTable = (int64_t)1 << 22; // K * B entries of the bucketing table
+constexpr int kMaxTiles = 2000;               // bucketing LDS (staging + tables) fits in 64 KB
+constexpr int kUnitLog = 12;                  // events per bucketing unit (workgroup): 4096
 constexpr int kChunk = 2048;
 
 struct DiagDev {
@@ -60,6 +60,8 @@ struct StateDev {
 
 // Units per segment of the column-wise table scan (at most 64 segments).
 int scan_segment_units(int64_t B);
+// LDS bytes of the bucketing kernel for K tiles.
+size_t bucket_lds_bytes(int K);
 
 // Kernel launchers (asynchronous on `stream`; return the launch error).
 hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule& sc,

@@ -65,22 +65,29 @@ __device__ __forceinline__ int first_frame_at_or_after(const int64_t* tf, int lo
 
 template <int PPT>
 struct Pixels {
+    // state after every event applied so far (Alg. 2)
     double S[PPT];
-    double u[PPT];      // 1 - k (t_f - T) at the last frame time written
     int64_t T[PPT];
     uint32_t N[PPT];
     int32_t P[PPT];
-    bool fresh[PPT];    // u is valid (no event since the last frame)
+    // the state as the frames see it: after the events up to the last
+    // frame written
+    double Sf[PPT];
+    int64_t Tf[PPT];
+    double u[PPT];      // 1 - k (t_f - Tf) at the last frame time written
+    bool fresh[PPT];    // u is valid (Tf unchanged since the last frame)
 };
 
-// Frames [j0, j1) with the events of the current chunk interleaved
-// (ptr/end/tn: each pixel's next event in `sorted`).
+// Phase B: frames [j0, j1).  Each pixel's events of the chunk were applied in
+// phase A, which left the state after each event in post_S; here a pixel only
+// moves its pointer past the events with t <= t_f and takes the state of the
+// last one (ptr/end/tn: the pixel's next event in `sorted` and its time).
 template <int PPT, int BK>
 __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>& px,
                                             const FrameOut& fo, int j0, int j1, int64_t& tf_prev,
-                                            const uint64_t* sorted, uint32_t* ptr,
-                                            const uint32_t* end, int64_t* tn, int64_t t_ref,
-                                            int64_t q0, int64_t npix)
+                                            const uint64_t* sorted, const double* post_S,
+                                            uint32_t* ptr, const uint32_t* end, int64_t* tn,
+                                            int64_t t_ref, int64_t q0, int64_t npix)
 {
     int64_t t_next_f = (j0 < j1) ? load_const(fo.t_frames, j0) : 0;
     for (int j = j0; j < j1; ++j) {
@@ -92,20 +99,22 @@ __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>&
         float F[PPT];
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            while (ptr[i] < end[i] && tn[i] <= t_f) {
-                const uint64_t r = sorted[ptr[i]];
-                apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], tn[i], record_pos(r));
+            if (ptr[i] < end[i] && tn[i] <= t_f) {
+                do {
+                    px.Sf[i] = post_S[ptr[i]];
+                    px.Tf[i] = tn[i];
+                    ++ptr[i];
+                    tn[i] = (ptr[i] < end[i]) ? t_ref + record_dt(sorted[ptr[i]]) : INT64_MAX;
+                } while (ptr[i] < end[i] && tn[i] <= t_f);
                 px.fresh[i] = false;
-                ++ptr[i];
-                tn[i] = (ptr[i] < end[i]) ? t_ref + record_dt(sorted[ptr[i]]) : INT64_MAX;
             }
             if (px.fresh[i]) {
                 px.u[i] -= dk;
             } else {
-                px.u[i] = __fma_rn(-mp.k, (double)(t_f - px.T[i]), 1.0);
+                px.u[i] = __fma_rn(-mp.k, (double)(t_f - px.Tf[i]), 1.0);
                 px.fresh[i] = true;
             }
-            F[i] = frame_value_u<BK>(mp, px.S[i], px.u[i]);
+            F[i] = frame_value_u<BK>(mp, px.Sf[i], px.u[i]);
         }
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
@@ -131,6 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
     constexpr int PER_WAVE = kChunk / kWavesPerBlock;     // records per wave per chunk
     constexpr int STEPS = PER_WAVE / kWave;               // records per lane per chunk
     __shared__ uint64_t sorted[kChunk];
+    __shared__ double post_S[kChunk];
     __shared__ uint32_t cnt[kWavesPerBlock][TILE];
     __shared__ uint32_t scan_w[kWavesPerBlock];
 
@@ -151,6 +161,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         px.T[i] = in ? st.T[q] : 0;
         px.N[i] = in ? st.N[q] : 0u;
         px.P[i] = in ? st.P[q] : 0;
+        px.Sf[i] = px.S[i];
+        px.Tf[i] = px.T[i];
         px.u[i] = 1.0;
         px.fresh[i] = false;
     }
@@ -253,14 +265,22 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         }
         __syncthreads();
 
-        // 3. frames that this chunk completes, with its events interleaved
+        // 3. phase A: each pixel's events of the chunk, in array order
+        // (Alg. 2 event loop); the state after each event goes to post_S
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             const int l = tid + i * kBlock;
             end[i] = min((l + 1 < TILE) ? cnt[0][l + 1] : (uint32_t)cn, (uint32_t)cn);
             ptr[i] = min(cnt[0][l], end[i]);
+            for (uint32_t e = ptr[i]; e < end[i]; ++e) {
+                const uint64_t r = sorted[e];
+                apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t_ref + record_dt(r),
+                                record_pos(r));
+                post_S[e] = px.S[i];
+            }
             tn[i] = (ptr[i] < end[i]) ? t_ref + record_dt(sorted[ptr[i]]) : INT64_MAX;
         }
+        // 4. phase B: the frames this chunk completes
         const int j_end = (t_next == INT64_MAX)
                               ? fo.nf
                               : first_frame_at_or_after(fo.t_frames, j, fo.nf, t_next);
@@ -269,17 +289,16 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         // which have had the whole sort to complete.  Waiting after this
         // chunk's stores instead would stall on all of them.
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        walk_frames<PPT, BK>(mp, px, fo, j, j_end, tf_prev, sorted, ptr, end, tn, t_ref, q0,
-                             npix);
+        walk_frames<PPT, BK>(mp, px, fo, j, j_end, tf_prev, sorted, post_S, ptr, end, tn, t_ref,
+                             q0, npix);
         j = j_end;
+        // the frames of later chunks see every event of this one
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            while (ptr[i] < end[i]) {
-                const uint64_t r = sorted[ptr[i]];
-                apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t_ref + record_dt(r),
-                                record_pos(r));
+            if (px.Tf[i] != px.T[i] || ptr[i] < end[i]) {
+                px.Sf[i] = px.S[i];
+                px.Tf[i] = px.T[i];
                 px.fresh[i] = false;
-                ++ptr[i];
             }
         }
 #pragma unroll
@@ -294,7 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         end[i] = 0;
         tn[i] = INT64_MAX;
     }
-    walk_frames<PPT, BK>(mp, px, fo, j, fo.nf, tf_prev, sorted, ptr, end, tn, t_ref, q0, npix);
+    walk_frames<PPT, BK>(mp, px, fo, j, fo.nf, tf_prev, sorted, post_S, ptr, end, tn, t_ref, q0,
+                         npix);
 
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {

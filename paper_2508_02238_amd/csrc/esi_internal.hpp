@@ -23,7 +23,7 @@ struct Schedule {
 
 constexpr int kMaxTiles = 2000;               // bucketing LDS (staging + tables) fits in 64 KB
 constexpr int kUnitLog = 12;                  // events per bucketing unit (workgroup): 4096
-constexpr int kChunk = 2048;
+constexpr int kChunk = 1792;
 
 struct DiagDev {
     unsigned long long dropped;

@@ -6,23 +6,27 @@
 // (S, T, N, P) stays in registers for the whole call, S in FP64.
 //
 // The tile's records (array order inside the tile, from the bucketing pass)
-// are consumed in chunks of kChunk:
-//   1. each wave loads its quarter of the chunk into registers;
+// are consumed in chunks of at most CHUNK records that complete at most
+// kFrameGroup frames:
+//   1. each wave holds its quarter of the chunk's records in registers
+//      (prefetched while the previous chunk was processed);
 //   2. stable counting sort by pixel inside the tile: per-wave stable ranks,
 //      an exclusive scan over (pixel, wave) counters, a scatter into LDS, so
 //      each pixel's events of the chunk are contiguous and in array order;
-//   3. every frame j with t_frames[j] earlier than the next chunk's first
-//      event is complete after this chunk: for each such frame each thread
-//      applies its pixels' events with t <= t_frames[j] (Alg. 2 event loop)
-//      and writes the frame value (Eq. (14)); then it applies the rest of
-//      the chunk.
+//   3. phase A: each thread runs the events of its pixels through Alg. 2 in
+//      array order and records a change list: for every frame of the chunk
+//      at which the pixel's visible state changes, the frame index and the
+//      state after the last event that frame includes;
+//   4. phase B: the chunk's frames, every thread writing its pixels' values
+//      (Eq. (14)); a frame only compares its index with the pixel's next
+//      change and selects, with no branch and no loop per event.
 // Frames after the last event are written from the final state.
 //
-// The frame loop index and the frame times are wave-uniform (scalar loads):
-// on CDNA a wait for a vector load also waits for every earlier store, so a
-// per-frame vector load would stall on the previous frame's stores.
-// Between events the decayed snapshot is advanced incrementally:
-// u = 1 - k (t_f - T) drops by k (t_f - t_f') from one frame to the next.
+// Frame times are read through the scalar path (wave-uniform index): on
+// CDNA one counter tracks vector loads and stores, and waiting for a vector
+// load issued after a burst of frame stores would wait for the stores too.
+// For the same reason the next chunk's records and frame times are loaded
+// before this chunk's frame stores and waited for in one place.
 #include <hip/hip_runtime.h>
 
 #include "esi_internal.hpp"
@@ -32,6 +36,12 @@ namespace {
 
 // s_waitcnt immediate (gfx9 encoding): vmcnt = 0, expcnt and lgkmcnt not waited.
 constexpr int kWaitVmcnt0 = 0x0F70;
+constexpr int kFrameGroup = 128;  // frames completed by one chunk, at most
+constexpr bool kMaskedReload = true;
+
+// Records per chunk: LDS holds the chunk three times over (records, states,
+// frame indices) next to the (pixel, wave) counters of the tile.
+constexpr int chunk_records(int ppt) { return ppt >= 4 ? 1024 : 1792; }
 
 struct FrameOut {
     const int64_t* t_frames;
@@ -40,22 +50,41 @@ struct FrameOut {
     uint8_t* frames_u8;
 };
 
-__device__ __forceinline__ int64_t uniform64(int64_t v)
+// First index in [lo, hi) whose frame time is >= t (hi if none); frame times
+// are non-decreasing (otherwise the result is some index in [lo, hi]).
+__device__ __forceinline__ int first_frame_at_or_after(const int64_t* tf, int lo, int hi, int64_t t)
 {
-    const uint64_t u = (uint64_t)v;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// First index in [lo, nf) whose frame time is >= t (nf if none); frame times
-// are non-decreasing (otherwise the result is some index in [lo, nf]).
-__device__ __forceinline__ int first_frame_at_or_after(const int64_t* tf, int lo, int nf, int64_t t)
-{
-    int hi = nf;
     while (lo < hi) {
         const int mid = lo + ((hi - lo) >> 1);
         if (load_const(tf, mid) < t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// First record index in [lo, hi) whose time is > t (hi if none).
+__device__ __forceinline__ uint32_t first_record_after(const uint64_t* rec, uint32_t lo, uint32_t hi,
+                                                       int64_t t_ref, int64_t t)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (t_ref + record_dt(load_const(rec, mid)) <= t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// First index in [0, n) of the LDS frame-time window with tfl[idx] >= t.
+__device__ __forceinline__ int lds_lower_bound(const int64_t* tfl, int n, int64_t t)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tfl[mid] < t)
             lo = mid + 1;
         else
             hi = mid;
@@ -70,61 +99,79 @@ struct Pixels {
     int64_t T[PPT];
     uint32_t N[PPT];
     int32_t P[PPT];
-    // the state as the frames see it: after the events up to the last
-    // frame written
-    double Sf[PPT];
-    int64_t Tf[PPT];
-    double u[PPT];      // 1 - k (t_f - Tf) at the last frame time written
-    bool fresh[PPT];    // u is valid (Tf unchanged since the last frame)
+    // the state the frames see (after the events up to the last frame
+    // written): Sf and Af = 1 + k (Tf - t_base), so that the decay base of a
+    // frame at t_f is u = Af - k (t_f - t_base)
+    double Sf[PPT], Af[PPT];
+    // this chunk's change list: entries cbase + idx, ... of chg_*
+    uint32_t cbase[PPT], nch[PPT], idx[PPT];
+    int jn[PPT];        // frame index (in the chunk) of the next change
+    double Sn[PPT], An[PPT];  // its state
 };
 
-// Phase B: frames [j0, j1).  Each pixel's events of the chunk were applied in
-// phase A, which left the state after each event in post_S; here a pixel only
-// moves its pointer past the events with t <= t_f and takes the state of the
-// last one (ptr/end/tn: the pixel's next event in `sorted` and its time).
-template <int PPT, int BK>
+// Phase B: frames [j0, j1) of the call.  jj = j - j0 indexes the chunk's
+// change lists and kt[jj] = k (t_f - t_base) (kt == nullptr: computed here).
+// Per pixel and frame: take the next change if it belongs to this frame
+// (only those lanes touch LDS), then v = clamp(Sf u^b), u = clamp(Af - kt, 0, 1),
+// F = (v - s_min)/(s_max - s_min).
+template <int PPT, int BK, int CHUNK_ENTRIES>
 __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>& px,
-                                            const FrameOut& fo, int j0, int j1, int64_t& tf_prev,
-                                            const uint64_t* sorted, const double* post_S,
-                                            uint32_t* ptr, const uint32_t* end, int64_t* tn,
-                                            int64_t t_ref, int64_t q0, int64_t npix)
+                                            const FrameOut& fo, int j0, int j1, int64_t t_base,
+                                            const double* kt, const double* chg_S,
+                                            const double* chg_A, const uint16_t* chg_j,
+                                            int64_t q0, int64_t npix)
 {
-    int64_t t_next_f = (j0 < j1) ? load_const(fo.t_frames, j0) : 0;
+    int64_t t_next_f = (j0 < j1 && !kt) ? load_const(fo.t_frames, j0) : 0;
     for (int j = j0; j < j1; ++j) {
-        const int64_t t_f = t_next_f;
-        if (j + 1 < j1)
-            t_next_f = load_const(fo.t_frames, j + 1);  // one frame ahead
-        const double dk = mp.k * (double)(t_f - tf_prev);
-        tf_prev = t_f;
+        const int jj = j - j0;
+        double ktf;
+        if (kt) {
+            ktf = kt[jj];
+        } else {
+            ktf = mp.k * (double)(t_next_f - t_base);
+            if (j + 1 < j1)
+                t_next_f = load_const(fo.t_frames, j + 1);  // one frame ahead
+        }
         float F[PPT];
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            if (ptr[i] < end[i] && tn[i] <= t_f) {
-                do {
-                    px.Sf[i] = post_S[ptr[i]];
-                    px.Tf[i] = tn[i];
-                    ++ptr[i];
-                    tn[i] = (ptr[i] < end[i]) ? t_ref + record_dt(sorted[ptr[i]]) : INT64_MAX;
-                } while (ptr[i] < end[i] && tn[i] <= t_f);
-                px.fresh[i] = false;
-            }
-            if (px.fresh[i]) {
-                px.u[i] -= dk;
+            if (kMaskedReload) {
+                if (px.jn[i] == jj) {
+                    px.Sf[i] = px.Sn[i];
+                    px.Af[i] = px.An[i];
+                    ++px.idx[i];
+                    const uint32_t e = min(px.cbase[i] + px.idx[i], (uint32_t)(CHUNK_ENTRIES - 1));
+                    px.Sn[i] = chg_S[e];
+                    px.An[i] = chg_A[e];
+                    px.jn[i] = (px.idx[i] < px.nch[i]) ? (int)chg_j[e] : 0x7FFFFFFF;
+                }
             } else {
-                px.u[i] = __fma_rn(-mp.k, (double)(t_f - px.Tf[i]), 1.0);
-                px.fresh[i] = true;
+                const bool c = px.jn[i] == jj;
+                px.Sf[i] = c ? px.Sn[i] : px.Sf[i];
+                px.Af[i] = c ? px.An[i] : px.Af[i];
+                px.idx[i] += c ? 1u : 0u;
+                const uint32_t e = min(px.cbase[i] + px.idx[i], (uint32_t)(CHUNK_ENTRIES - 1));
+                px.Sn[i] = chg_S[e];
+                px.An[i] = chg_A[e];
+                px.jn[i] = (px.idx[i] < px.nch[i]) ? (int)chg_j[e] : 0x7FFFFFFF;
             }
-            F[i] = frame_value_u<BK>(mp, px.Sf[i], px.u[i]);
+            double v = px.Sf[i];
+            if (!mp.lazy) {
+                const double u = fmin(fmax(px.Af[i] - ktf, 0.0), 1.0);
+                v = clamp_s(mp, px.Sf[i] * power_b<BK>(u, mp.b));
+            }
+            F[i] = (float)((v - mp.s_min) * mp.inv_range);
         }
+        float* frow = fo.frames ? fo.frames + (size_t)j * (size_t)npix : nullptr;
+        uint8_t* urow = fo.frames_u8 ? fo.frames_u8 + (size_t)j * (size_t)npix : nullptr;
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             const int64_t q = q0 + (int64_t)i * kBlock;
             if (q < npix) {
-                const size_t o = (size_t)j * (size_t)npix + (size_t)q;
-                if (fo.frames)
-                    __builtin_nontemporal_store(F[i], fo.frames + o);
-                if (fo.frames_u8)
-                    fo.frames_u8[o] = frame_code(F[i]);
+                if (frow)
+                    __builtin_nontemporal_store(F[i], frow + q);
+                if (urow)
+                    urow[q] = frame_code(F[i]);
             }
         }
     }
@@ -137,12 +184,19 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
     MethodParams mp, FrameOut fo, DiagDev* diag)
 {
     constexpr int TILE = kBlock * PPT;
-    constexpr int PER_WAVE = kChunk / kWavesPerBlock;     // records per wave per chunk
+    constexpr int CHUNK = chunk_records(PPT);             // records per chunk, at most
+    constexpr int PER_WAVE = CHUNK / kWavesPerBlock;      // records per wave per chunk
     constexpr int STEPS = PER_WAVE / kWave;               // records per lane per chunk
-    __shared__ uint64_t sorted[kChunk];
-    __shared__ double post_S[kChunk];
+    static_assert(kFrameGroup <= kBlock, "one frame time per thread");
+    static_assert(PER_WAVE % kWave == 0, "chunk size");
+    __shared__ uint64_t sorted[CHUNK];    // records sorted by pixel; then event times (double)
+    __shared__ double chg_S[CHUNK];       // change lists: S after the change
+    __shared__ uint16_t chg_j[CHUNK];     // change lists: frame index in the chunk
     __shared__ uint32_t cnt[kWavesPerBlock][TILE];
+    __shared__ int64_t tfl[kFrameGroup];  // frame times of the chunk
+    __shared__ double ktl[kFrameGroup];   // k (t_f - t_base) of the chunk's frames
     __shared__ uint32_t scan_w[kWavesPerBlock];
+    double* chg_A = (double*)sorted;      // change lists: A after the change
 
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
@@ -162,9 +216,12 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         px.N[i] = in ? st.N[q] : 0u;
         px.P[i] = in ? st.P[q] : 0;
         px.Sf[i] = px.S[i];
-        px.Tf[i] = px.T[i];
-        px.u[i] = 1.0;
-        px.fresh[i] = false;
+        px.cbase[i] = 0;
+        px.nch[i] = 0;
+        px.idx[i] = 0;
+        px.jn[i] = 0x7FFFFFFF;
+        px.Sn[i] = 0.0;
+        px.An[i] = 0.0;
     }
 
     // the tile's records [rs, re); read-only here, so scalar loads
@@ -176,36 +233,62 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         t_ref = load_const(ev_t, 0);
     }
 
-    int j = 0;               // next frame to write (uniform)
-    int64_t tf_prev = 0;     // time of the last frame written (uniform)
-    bool bad = false;
-    uint32_t ptr[PPT], end[PPT];
-    int64_t tn[PPT];
+    // frame decay bases are measured from t_base (first frame time) so that
+    // A = 1 + k (T - t_base) keeps its precision
+    const int64_t t_base = (fo.nf > 0) ? load_const(fo.t_frames, 0) : 0;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i)
+        px.Af[i] = __fma_rn(mp.k, (double)(px.T[i] - t_base), 1.0);
 
-    // Records of a chunk, this wave's quarter, step-major (array order).
-    // Clamped indices: no select on loaded values, all loads stay in flight.
+    int j = 0;  // next frame to write (uniform)
+    bool bad = false;
+
+    // records of the first chunk and the first frame times; clamped indices,
+    // no select on loaded values, so all loads stay in flight
     uint64_t rr[STEPS], rr_next[STEPS];
+    int64_t tf_cur = 0, tf_nxt = 0;
     if (rs < re) {
-        const int cn0 = (int)(min(rs + (uint32_t)kChunk, re) - rs);
+        const int cn0 = (int)(min(rs + (uint32_t)CHUNK, re) - rs);
 #pragma unroll
         for (int s = 0; s < STEPS; ++s)
             rr[s] = records[rs + min(wave * PER_WAVE + s * kWave + lane, cn0 - 1)];
+        if (fo.nf > 0)
+            tf_cur = fo.t_frames[min(tid, fo.nf - 1)];
     }
     // nothing may be pending on `rr` at the loop head, or the compiler waits
     // there for everything outstanding, frame stores included
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-    for (uint32_t cs = rs; cs < re; cs += kChunk) {
-        const uint32_t ce = min(cs + (uint32_t)kChunk, re);
+
+    for (uint32_t cs = rs; cs < re;) {
+        // this chunk: at most CHUNK records, completing at most kFrameGroup
+        // frames (records after the group's last frame wait for the next one)
+        uint32_t ce = min(cs + (uint32_t)CHUNK, re);
+        const int jmax = min(j + kFrameGroup, fo.nf);
+        if (j < fo.nf && jmax < fo.nf)
+            ce = first_record_after(records, cs, ce, t_ref, load_const(fo.t_frames, jmax - 1));
         const int cn = (int)(ce - cs);
         const int64_t t_next = (ce < re) ? t_ref + record_dt(load_const(records, ce)) : INT64_MAX;
-        // prefetch the next chunk before this chunk's frame stores are issued
+        int j_end = (t_next == INT64_MAX) ? jmax
+                                          : min(first_frame_at_or_after(fo.t_frames, j, fo.nf, t_next), jmax);
+        if (cn == 0 && j_end == j)
+            j_end = min(j + 1, fo.nf);  // progress even with unsorted frame times
+        const int nfw = j_end - j;     // frames of this chunk
+
+        // prefetch the next chunk's records and frame times (before this
+        // chunk's frame stores are issued)
         if (ce < re) {
-            const int cn1 = (int)(min(ce + (uint32_t)kChunk, re) - ce);
+            const int cn1 = (int)(min(ce + (uint32_t)CHUNK, re) - ce);
 #pragma unroll
             for (int s = 0; s < STEPS; ++s)
                 rr_next[s] = records[ce + min(wave * PER_WAVE + s * kWave + lane, cn1 - 1)];
         }
+        if (j_end < fo.nf)
+            tf_nxt = fo.t_frames[min(j_end + tid, fo.nf - 1)];
 
+        if (tid < kFrameGroup) {
+            tfl[tid] = tf_cur;
+            ktl[tid] = mp.k * (double)(tf_cur - t_base);
+        }
         // 2a. stable ranks inside the wave
         for (int k = lane; k < TILE; k += kWave)
             cnt[wave][k] = 0;
@@ -214,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
 #pragma unroll
         for (int s = 0; s < STEPS; ++s) {
             const int c = wave * PER_WAVE + s * kWave + lane;
-            rank[s] = wave_stable_rank(c < cn, (record_lpx(rr[s]) & (TILE - 1)), kbits, cnt[wave]);
+            rank[s] = wave_stable_rank(c < cn, record_lpx(rr[s]) & (TILE - 1), kbits, cnt[wave]);
         }
         __syncthreads();
         // 2b. exclusive scan over (pixel, wave), pixel-major
@@ -256,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         for (int s = 0; s < STEPS; ++s) {
             const int c = wave * PER_WAVE + s * kWave + lane;
             if (c < cn) {
-                const uint32_t at = cnt[wave][(record_lpx(rr[s]) & (TILE - 1))] + rank[s];
+                const uint32_t at = cnt[wave][record_lpx(rr[s]) & (TILE - 1)] + rank[s];
                 if (at < (uint32_t)cn)
                     sorted[at] = rr[s];
                 else
@@ -265,56 +348,67 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         }
         __syncthreads();
 
-        // 3. phase A: each pixel's events of the chunk, in array order
-        // (Alg. 2 event loop); the state after each event goes to post_S
+        // 3. phase A: each pixel's events of the chunk in array order; the
+        // change list keeps, per frame index jc of the chunk that first
+        // includes some event, the state after the last such event.  Entries
+        // go over the pixel's own slots of `sorted`/chg_*, behind the read
+        // position.  Events after the chunk's last frame (jc == nfw) make no
+        // entry: the frames of later chunks see the final state.
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             const int l = tid + i * kBlock;
-            end[i] = min((l + 1 < TILE) ? cnt[0][l + 1] : (uint32_t)cn, (uint32_t)cn);
-            ptr[i] = min(cnt[0][l], end[i]);
-            for (uint32_t e = ptr[i]; e < end[i]; ++e) {
+            const uint32_t end = min((l + 1 < TILE) ? cnt[0][l + 1] : (uint32_t)cn, (uint32_t)cn);
+            const uint32_t beg = min(cnt[0][l], end);
+            uint32_t w = beg;          // change list write position
+            int jc_prev = -1;
+            for (uint32_t e = beg; e < end; ++e) {
                 const uint64_t r = sorted[e];
-                apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t_ref + record_dt(r),
-                                record_pos(r));
-                post_S[e] = px.S[i];
+                const int64_t t = t_ref + record_dt(r);
+                apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t, record_pos(r));
+                const int jc = lds_lower_bound(tfl, nfw, t);
+                if (jc < nfw) {
+                    if (jc != jc_prev && jc_prev >= 0)
+                        ++w;           // a new entry; the previous one is final
+                    chg_S[w] = px.S[i];
+                    chg_A[w] = __fma_rn(mp.k, (double)(t - t_base), 1.0);
+                    chg_j[w] = (uint16_t)jc;
+                    jc_prev = jc;
+                }
             }
-            tn[i] = (ptr[i] < end[i]) ? t_ref + record_dt(sorted[ptr[i]]) : INT64_MAX;
+            px.cbase[i] = beg;
+            px.nch[i] = (jc_prev >= 0) ? (w - beg + 1u) : 0u;
+            px.idx[i] = 0;
+            const uint32_t e0 = min(beg, (uint32_t)max(cn - 1, 0));
+            px.jn[i] = px.nch[i] ? (int)chg_j[e0] : 0x7FFFFFFF;
+            px.Sn[i] = chg_S[e0];
+            px.An[i] = chg_A[e0];
         }
-        // 4. phase B: the frames this chunk completes
-        const int j_end = (t_next == INT64_MAX)
-                              ? fo.nf
-                              : first_frame_at_or_after(fo.t_frames, j, fo.nf, t_next);
-        // Wait for the prefetched records now: this also drains the frame
-        // stores of the previous chunk (one counter covers loads and stores),
-        // which have had the whole sort to complete.  Waiting after this
-        // chunk's stores instead would stall on all of them.
+        // Wait for the prefetched records and frame times now: this also
+        // drains the frame stores of the previous chunk (one counter covers
+        // loads and stores), which have had the whole sort to complete.
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        walk_frames<PPT, BK>(mp, px, fo, j, j_end, tf_prev, sorted, post_S, ptr, end, tn, t_ref,
-                             q0, npix);
+        // 4. phase B: the frames this chunk completes
+        walk_frames<PPT, BK, CHUNK>(mp, px, fo, j, j_end, t_base, ktl, chg_S, chg_A, chg_j, q0,
+                                    npix);
         j = j_end;
         // the frames of later chunks see every event of this one
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            if (px.Tf[i] != px.T[i] || ptr[i] < end[i]) {
-                px.Sf[i] = px.S[i];
-                px.Tf[i] = px.T[i];
-                px.fresh[i] = false;
-            }
+            px.Sf[i] = px.S[i];
+            px.Af[i] = __fma_rn(mp.k, (double)(px.T[i] - t_base), 1.0);
+            px.nch[i] = 0;
+            px.jn[i] = 0x7FFFFFFF;
         }
 #pragma unroll
         for (int s = 0; s < STEPS; ++s)
             rr[s] = rr_next[s];
+        tf_cur = tf_nxt;
+        cs = ce;
         __syncthreads();  // LDS is reused by the next chunk
     }
-    // frames after the last event
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-        ptr[i] = 0;
-        end[i] = 0;
-        tn[i] = INT64_MAX;
-    }
-    walk_frames<PPT, BK>(mp, px, fo, j, fo.nf, tf_prev, sorted, post_S, ptr, end, tn, t_ref, q0,
-                         npix);
+    // frames after the last event (no change lists: nch = 0, jn never hit)
+    walk_frames<PPT, BK, CHUNK>(mp, px, fo, j, fo.nf, t_base, nullptr, chg_S, chg_A, chg_j, q0,
+                                npix);
 
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {

@@ -63,6 +63,7 @@ MethodParams method_params(const esi_params& p)
     mp.s_min = p.s_min;
     mp.s_max = p.s_max;
     mp.inv_range = 1.0 / (p.s_max - p.s_min);
+    mp.f_off = -p.s_min * mp.inv_range;
     mp.decay_then_add = (p.flags & ESI_DECAY_THEN_ADD) ? 1 : 0;
     mp.lazy = (p.flags & ESI_SNAPSHOT_LAZY) ? 1 : 0;
     return mp;

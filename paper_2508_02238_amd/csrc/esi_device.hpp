@@ -20,6 +20,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 // Per-call constants of the method.
 struct MethodParams {
     double C, k, b, s_min, s_max, inv_range;  // inv_range = 1 / (s_max - s_min)
+    double f_off;                             // -s_min * inv_range
     int decay_then_add;
     int lazy;
 };

@@ -6,27 +6,38 @@
 // (S, T, N, P) stays in registers for the whole call, S in FP64.
 //
 // The tile's records (array order inside the tile, from the bucketing pass)
-// are consumed in chunks of at most CHUNK records that complete at most
-// kFrameGroup frames:
+// are consumed in chunks of at most CHUNK records, each paired with a
+// segment of at most kFrameGroup frames: the frames that every record of the
+// chunk precedes or belongs to and that no later record can reach.
 //   1. each wave holds its quarter of the chunk's records in registers
 //      (prefetched while the previous chunk was processed);
-//   2. stable counting sort by pixel inside the tile: per-wave stable ranks,
-//      an exclusive scan over (pixel, wave) counters, a scatter into LDS, so
-//      each pixel's events of the chunk are contiguous and in array order;
+//   2. each record finds the first frame of the segment that includes it (a
+//      fixed-step search over the segment's frame times in LDS), then a
+//      stable counting sort by pixel inside the tile (per-wave stable ranks,
+//      an exclusive scan over (pixel, wave) counters, a scatter into LDS) makes
+//      each pixel's events of the chunk contiguous and in array order;
 //   3. phase A: each thread runs the events of its pixels through Alg. 2 in
-//      array order and records a change list: for every frame of the chunk
+//      array order and records a change list: for every frame of the segment
 //      at which the pixel's visible state changes, the frame index and the
 //      state after the last event that frame includes;
-//   4. phase B: the chunk's frames, every thread writing its pixels' values
-//      (Eq. (14)); a frame only compares its index with the pixel's next
-//      change and selects, with no branch and no loop per event.
-// Frames after the last event are written from the final state.
+//   4. phase B: the segment's frames, every thread writing its pixels' values
+//      (Eq. (14)); a frame compares its index with the pixel's next change
+//      and only lanes with a change touch LDS.
+// Frames after the last event form segments with no records.
 //
-// Frame times are read through the scalar path (wave-uniform index): on
-// CDNA one counter tracks vector loads and stores, and waiting for a vector
-// load issued after a burst of frame stores would wait for the stores too.
-// For the same reason the next chunk's records and frame times are loaded
-// before this chunk's frame stores and waited for in one place.
+// Decay at a frame: with t_b the segment's first frame time, a visible state
+// (S, T) keeps A = 1 + k (T - t_b) and a frame at t_f has kt = k (t_f - t_b),
+// so the base of Eq. (4) is u = A - kt = 1 - k (t_f - T).  A segment's frames
+// span at most kMaxSegmentDecay decay lengths, which bounds the rounding of u
+// by a few ulp of that span (a longer gap gives a one-frame segment, kt = 0).
+//
+// Chunk boundaries come from a few scalar loads (first and last record of
+// the window, first frame time after it) prefetched one chunk ahead; only a
+// chunk that ends because its frame segment is full searches the records.
+// The next chunk's records and frame times are loaded before this chunk's
+// frame stores and waited for in one place: on CDNA one counter tracks vector
+// loads and stores, and a load waited for after a burst of stores would wait
+// for the stores too.
 #include <hip/hip_runtime.h>
 
 #include "esi_internal.hpp"
@@ -36,12 +47,21 @@ namespace {
 
 // s_waitcnt immediate (gfx9 encoding): vmcnt = 0, expcnt and lgkmcnt not waited.
 constexpr int kWaitVmcnt0 = 0x0F70;
-constexpr int kFrameGroup = 128;  // frames completed by one chunk, at most
-constexpr bool kMaskedReload = true;
+constexpr int kFrameGroup = 128;                    // frames per segment, at most
+constexpr double kMaxSegmentDecay = 1073741824.0;   // 2^30
+constexpr int kNever = 0x7FFFFFFF;                  // "no further change"
+constexpr uint64_t kLpxMask = (uint64_t)0x7FFF << 48;
 
-// Records per chunk: LDS holds the chunk three times over (records, states,
-// frame indices) next to the (pixel, wave) counters of the tile.
-constexpr int chunk_records(int ppt) { return ppt >= 4 ? 1024 : 1792; }
+template <int PPT>
+struct TileCfg {
+    static constexpr int TILE = kBlock * PPT;
+    // records per chunk: LDS holds them three times over (records, states,
+    // frame indices) next to the (pixel, wave) counters of the tile; sized so
+    // that five workgroups of one pixel per thread share a CU
+    static constexpr int CHUNK = PPT == 1 ? 1536 : (PPT == 2 ? 1280 : 1024);
+    static constexpr int PER_WAVE = CHUNK / kWavesPerBlock;  // records per wave per chunk
+    static constexpr int STEPS = PER_WAVE / kWave;           // records per lane per chunk
+};
 
 struct FrameOut {
     const int64_t* t_frames;
@@ -50,21 +70,8 @@ struct FrameOut {
     uint8_t* frames_u8;
 };
 
-// First index in [lo, hi) whose frame time is >= t (hi if none); frame times
-// are non-decreasing (otherwise the result is some index in [lo, hi]).
-__device__ __forceinline__ int first_frame_at_or_after(const int64_t* tf, int lo, int hi, int64_t t)
-{
-    while (lo < hi) {
-        const int mid = lo + ((hi - lo) >> 1);
-        if (load_const(tf, mid) < t)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// First record index in [lo, hi) whose time is > t (hi if none).
+// First record index in [lo, hi) whose time is > t (hi if none); records of
+// a tile are in array order, so this is exact for time-sorted input.
 __device__ __forceinline__ uint32_t first_record_after(const uint64_t* rec, uint32_t lo, uint32_t hi,
                                                        int64_t t_ref, int64_t t)
 {
@@ -78,18 +85,22 @@ __device__ __forceinline__ uint32_t first_record_after(const uint64_t* rec, uint
     return lo;
 }
 
-// First index in [0, n) of the LDS frame-time window with tfl[idx] >= t.
-__device__ __forceinline__ int lds_lower_bound(const int64_t* tfl, int n, int64_t t)
+// Number of leading entries of tfl[0, n) that are < t (n <= kFrameGroup), in
+// a fixed number of steps; for non-decreasing tfl this is the lower bound.
+__device__ __forceinline__ int frames_before(const int64_t* tfl, int n, int64_t t)
 {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (tfl[mid] < t)
-            lo = mid + 1;
-        else
-            hi = mid;
+    int pos = 0;
+#pragma unroll
+    for (int step = kFrameGroup / 2; step >= 1; step >>= 1) {
+        const int probe = pos + step;
+        const int64_t v = tfl[min(probe, kFrameGroup) - 1];
+        pos = (probe <= n && v < t) ? probe : pos;
     }
-    return lo;
+    // the last entry (n == kFrameGroup) is covered by the steps above only
+    // up to kFrameGroup - 1
+    if (pos == kFrameGroup - 1 && n == kFrameGroup && tfl[kFrameGroup - 1] < t)
+        pos = kFrameGroup;
+    return pos;
 }
 
 template <int PPT>
@@ -99,82 +110,145 @@ struct Pixels {
     int64_t T[PPT];
     uint32_t N[PPT];
     int32_t P[PPT];
-    // the state the frames see (after the events up to the last frame
-    // written): Sf and Af = 1 + k (Tf - t_base), so that the decay base of a
-    // frame at t_f is u = Af - k (t_f - t_base)
+    // the state the frames see: Sf and Af = 1 + k (Tf - t_b)
     double Sf[PPT], Af[PPT];
-    // this chunk's change list: entries cbase + idx, ... of chg_*
-    uint32_t cbase[PPT], nch[PPT], idx[PPT];
-    int jn[PPT];        // frame index (in the chunk) of the next change
-    double Sn[PPT], An[PPT];  // its state
+    // change list of the segment: entries [.., cend) of chg_*, nx = next to load
+    uint32_t nx[PPT], cend[PPT];
+    int jn[PPT], jn2[PPT];      // frame indices of the next two changes
+    double Sn[PPT], An[PPT];    // the next change
+    double Sn2[PPT], An2[PPT];  // the one after
 };
 
-// Phase B: frames [j0, j1) of the call.  jj = j - j0 indexes the chunk's
-// change lists and kt[jj] = k (t_f - t_base) (kt == nullptr: computed here).
-// Per pixel and frame: take the next change if it belongs to this frame
-// (only those lanes touch LDS), then v = clamp(Sf u^b), u = clamp(Af - kt, 0, 1),
-// F = (v - s_min)/(s_max - s_min).
-template <int PPT, int BK, int CHUNK_ENTRIES>
-__device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>& px,
-                                            const FrameOut& fo, int j0, int j1, int64_t t_base,
-                                            const double* kt, const double* chg_S,
-                                            const double* chg_A, const uint16_t* chg_j,
-                                            int64_t q0, int64_t npix)
+template <int PPT, int CH>
+__device__ __forceinline__ void load_change(Pixels<PPT>& px, int i, const double* chg_S,
+                                            const double* chg_A, const uint16_t* chg_j, int& jv,
+                                            double& Sv, double& Av)
 {
-    int64_t t_next_f = (j0 < j1 && !kt) ? load_const(fo.t_frames, j0) : 0;
-    for (int j = j0; j < j1; ++j) {
-        const int jj = j - j0;
-        double ktf;
-        if (kt) {
-            ktf = kt[jj];
-        } else {
-            ktf = mp.k * (double)(t_next_f - t_base);
-            if (j + 1 < j1)
-                t_next_f = load_const(fo.t_frames, j + 1);  // one frame ahead
-        }
-        float F[PPT];
+    const uint32_t e = min(px.nx[i], (uint32_t)(CH - 1));
+    Sv = chg_S[e];
+    Av = chg_A[e];
+    jv = (px.nx[i] < px.cend[i]) ? (int)chg_j[e] : kNever;
+    ++px.nx[i];
+}
+
+// One frame (index jj of the segment) of Eq. (14): take the pixel's next
+// change if it belongs to this frame, then v = clamp(Sf u^b) with
+// u = clamp(Af - kt, 0, 1) (v = Sf for the lazy snapshot) and
+// F = (v - s_min) / (s_max - s_min).  OUT: 1 FP32 frames, 2 8-bit codes, 3 both.
+template <int PPT, int BK, bool LAZY, int OUT, int CH>
+__device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& px, int jj, double kt,
+                                           const double* chg_S, const double* chg_A,
+                                           const uint16_t* chg_j, float* frow, uint8_t* urow,
+                                           const uint32_t (&off)[PPT], const bool (&in)[PPT])
+{
 #pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-            if (kMaskedReload) {
-                if (px.jn[i] == jj) {
-                    px.Sf[i] = px.Sn[i];
-                    px.Af[i] = px.An[i];
-                    ++px.idx[i];
-                    const uint32_t e = min(px.cbase[i] + px.idx[i], (uint32_t)(CHUNK_ENTRIES - 1));
-                    px.Sn[i] = chg_S[e];
-                    px.An[i] = chg_A[e];
-                    px.jn[i] = (px.idx[i] < px.nch[i]) ? (int)chg_j[e] : 0x7FFFFFFF;
-                }
-            } else {
-                const bool c = px.jn[i] == jj;
-                px.Sf[i] = c ? px.Sn[i] : px.Sf[i];
-                px.Af[i] = c ? px.An[i] : px.Af[i];
-                px.idx[i] += c ? 1u : 0u;
-                const uint32_t e = min(px.cbase[i] + px.idx[i], (uint32_t)(CHUNK_ENTRIES - 1));
-                px.Sn[i] = chg_S[e];
-                px.An[i] = chg_A[e];
-                px.jn[i] = (px.idx[i] < px.nch[i]) ? (int)chg_j[e] : 0x7FFFFFFF;
-            }
-            double v = px.Sf[i];
-            if (!mp.lazy) {
-                const double u = fmin(fmax(px.Af[i] - ktf, 0.0), 1.0);
-                v = clamp_s(mp, px.Sf[i] * power_b<BK>(u, mp.b));
-            }
-            F[i] = (float)((v - mp.s_min) * mp.inv_range);
+    for (int i = 0; i < PPT; ++i) {
+        if (px.jn[i] == jj) {
+            px.Sf[i] = px.Sn[i];
+            px.Af[i] = px.An[i];
+            px.jn[i] = px.jn2[i];
+            px.Sn[i] = px.Sn2[i];
+            px.An[i] = px.An2[i];
+            load_change<PPT, CH>(px, i, chg_S, chg_A, chg_j, px.jn2[i], px.Sn2[i], px.An2[i]);
         }
-        float* frow = fo.frames ? fo.frames + (size_t)j * (size_t)npix : nullptr;
-        uint8_t* urow = fo.frames_u8 ? fo.frames_u8 + (size_t)j * (size_t)npix : nullptr;
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-            const int64_t q = q0 + (int64_t)i * kBlock;
-            if (q < npix) {
-                if (frow)
-                    __builtin_nontemporal_store(F[i], frow + q);
-                if (urow)
-                    urow[q] = frame_code(F[i]);
-            }
+        double v = px.Sf[i];
+        if (!LAZY) {
+            const double u = fmin(fmax(px.Af[i] - kt, 0.0), 1.0);
+            v = clamp_s(mp, v * power_b<BK>(u, mp.b));
+        }
+        const float F = (float)__fma_rn(v, mp.inv_range, mp.f_off);
+        if (in[i]) {
+            if (OUT & 1)
+                __builtin_nontemporal_store(F, frow + off[i]);
+            if (OUT & 2)
+                urow[off[i]] = frame_code(F);
         }
     }
+}
+
+// Phase B over the nfw frames of one segment; frow / urow point at the
+// tile's piece of the segment's first frame; ktl[jj] = k (t_f - t_b).
+template <int PPT, int BK, bool LAZY, int OUT, int CH>
+__device__ __forceinline__ void walk_segment(const MethodParams& mp, Pixels<PPT>& px, int nfw,
+                                             const double* ktl, const double* chg_S,
+                                             const double* chg_A, const uint16_t* chg_j,
+                                             float* frow, uint8_t* urow, int64_t npix,
+                                             const uint32_t (&off)[PPT], const bool (&in)[PPT])
+{
+    for (int jj = 0; jj < nfw; jj += 2) {
+        const double2 kk = *reinterpret_cast<const double2*>(ktl + jj);
+        frame_step<PPT, BK, LAZY, OUT, CH>(mp, px, jj, kk.x, chg_S, chg_A, chg_j, frow, urow, off, in);
+        if (OUT & 1)
+            frow += npix;
+        if (OUT & 2)
+            urow += npix;
+        if (jj + 1 < nfw) {
+            frame_step<PPT, BK, LAZY, OUT, CH>(mp, px, jj + 1, kk.y, chg_S, chg_A, chg_j, frow, urow,
+                                               off, in);
+            if (OUT & 1)
+                frow += npix;
+            if (OUT & 2)
+                urow += npix;
+        }
+    }
+}
+
+// Output mode of a call: 0-2 decayed snapshots (FP32, 8-bit, both), 3-5 lazy.
+__device__ __forceinline__ int walk_mode(const MethodParams& mp, const FrameOut& fo)
+{
+    const int out = (fo.frames && fo.frames_u8) ? 2 : (fo.frames ? 0 : 1);
+    return (mp.lazy ? 3 : 0) + out;
+}
+
+template <int PPT, int BK, int CH>
+__device__ __forceinline__ void walk_dispatch(int mode, const MethodParams& mp, Pixels<PPT>& px,
+                                              int nfw, const double* ktl, const double* chg_S,
+                                              const double* chg_A, const uint16_t* chg_j,
+                                              float* frow, uint8_t* urow, int64_t npix,
+                                              const uint32_t (&off)[PPT], const bool (&in)[PPT])
+{
+    switch (mode) {
+    case 0:
+        walk_segment<PPT, BK, false, 1, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
+        break;
+    case 1:
+        walk_segment<PPT, BK, false, 2, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
+        break;
+    case 2:
+        walk_segment<PPT, BK, false, 3, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
+        break;
+    case 3:
+        walk_segment<PPT, BK, true, 1, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
+        break;
+    case 4:
+        walk_segment<PPT, BK, true, 2, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
+        break;
+    default:
+        walk_segment<PPT, BK, true, 3, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
+        break;
+    }
+}
+
+// Scalars that place one chunk: its record window [cs, cs + avail), the
+// times of the window's last record and of the record after it, and the
+// frame times that bound its segment.
+struct ChunkCtl {
+    uint32_t avail;
+    int64_t t_last, t_after;  // t_after = INT64_MAX when the window ends the tile
+    int64_t tb, tf_hi;        // frame j and frame min(j + kFrameGroup, nf) - 1
+};
+
+template <int CHUNK>
+__device__ __forceinline__ ChunkCtl chunk_ctl(const uint64_t* records, uint32_t cs, uint32_t re,
+                                              int64_t t_ref, const FrameOut& fo, int j)
+{
+    ChunkCtl c;
+    c.avail = min((uint32_t)CHUNK, re - cs);
+    c.t_last = c.avail ? t_ref + record_dt(load_const(records, cs + c.avail - 1)) : 0;
+    c.t_after = (cs + c.avail < re) ? t_ref + record_dt(load_const(records, cs + c.avail)) : INT64_MAX;
+    c.tb = (j < fo.nf) ? load_const(fo.t_frames, j) : 0;
+    c.tf_hi = (j < fo.nf) ? load_const(fo.t_frames, min(j + kFrameGroup, fo.nf) - 1) : 0;
+    return c;
 }
 
 template <int PPT, int BK>
@@ -183,20 +257,22 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
     const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t, int K, StateDev st,
     MethodParams mp, FrameOut fo, DiagDev* diag)
 {
-    constexpr int TILE = kBlock * PPT;
-    constexpr int CHUNK = chunk_records(PPT);             // records per chunk, at most
-    constexpr int PER_WAVE = CHUNK / kWavesPerBlock;      // records per wave per chunk
-    constexpr int STEPS = PER_WAVE / kWave;               // records per lane per chunk
+    using Cfg = TileCfg<PPT>;
+    constexpr int TILE = Cfg::TILE;
+    constexpr int CHUNK = Cfg::CHUNK;
+    constexpr int PER_WAVE = Cfg::PER_WAVE;
+    constexpr int STEPS = Cfg::STEPS;
     static_assert(kFrameGroup <= kBlock, "one frame time per thread");
     static_assert(PER_WAVE % kWave == 0, "chunk size");
-    __shared__ uint64_t sorted[CHUNK];    // records sorted by pixel; then event times (double)
+    static_assert(CHUNK < 65536, "16-bit counters");
+    __shared__ uint64_t sorted[CHUNK];    // records sorted by pixel (frame index over the pixel field)
     __shared__ double chg_S[CHUNK];       // change lists: S after the change
-    __shared__ uint16_t chg_j[CHUNK];     // change lists: frame index in the chunk
-    __shared__ uint32_t cnt[kWavesPerBlock][TILE];
-    __shared__ int64_t tfl[kFrameGroup];  // frame times of the chunk
-    __shared__ double ktl[kFrameGroup];   // k (t_f - t_base) of the chunk's frames
+    __shared__ uint16_t chg_j[CHUNK];     // change lists: frame index in the segment
+    __shared__ uint16_t cnt[kWavesPerBlock][TILE];
+    __shared__ int64_t tfl[kFrameGroup];  // frame times of the segment
+    __shared__ __align__(16) double ktl[kFrameGroup];  // k (t_f - t_b) of the segment's frames
     __shared__ uint32_t scan_w[kWavesPerBlock];
-    double* chg_A = (double*)sorted;      // change lists: A after the change
+    double* chg_A = reinterpret_cast<double*>(sorted);  // change lists: A after the change
 
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
@@ -205,23 +281,21 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
     const int64_t q0 = (int64_t)tile * TILE + tid;
     const int64_t npix = st.npix;
     const int kbits = key_bits_for((uint32_t)TILE);
+    const int nf = fo.nf;
+    const int mode = walk_mode(mp, fo);
 
     Pixels<PPT> px;
+    uint32_t off[PPT];
+    bool in[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int64_t q = q0 + (int64_t)i * kBlock;
-        const bool in = q < npix;
-        px.S[i] = in ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
-        px.T[i] = in ? st.T[q] : 0;
-        px.N[i] = in ? st.N[q] : 0u;
-        px.P[i] = in ? st.P[q] : 0;
-        px.Sf[i] = px.S[i];
-        px.cbase[i] = 0;
-        px.nch[i] = 0;
-        px.idx[i] = 0;
-        px.jn[i] = 0x7FFFFFFF;
-        px.Sn[i] = 0.0;
-        px.An[i] = 0.0;
+        in[i] = q < npix;
+        off[i] = (uint32_t)(tid + i * kBlock);
+        px.S[i] = in[i] ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
+        px.T[i] = in[i] ? st.T[q] : 0;
+        px.N[i] = in[i] ? st.N[q] : 0u;
+        px.P[i] = in[i] ? st.P[q] : 0;
     }
 
     // the tile's records [rs, re); read-only here, so scalar loads
@@ -233,187 +307,213 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
         t_ref = load_const(ev_t, 0);
     }
 
-    // frame decay bases are measured from t_base (first frame time) so that
-    // A = 1 + k (T - t_base) keeps its precision
-    const int64_t t_base = (fo.nf > 0) ? load_const(fo.t_frames, 0) : 0;
-#pragma unroll
-    for (int i = 0; i < PPT; ++i)
-        px.Af[i] = __fma_rn(mp.k, (double)(px.T[i] - t_base), 1.0);
-
-    int j = 0;  // next frame to write (uniform)
+    int j = 0;  // first frame of the segment (uniform)
+    uint32_t cs = rs;
     bool bad = false;
+    ChunkCtl c = chunk_ctl<CHUNK>(records, cs, re, t_ref, fo, j);
 
     // records of the first chunk and the first frame times; clamped indices,
     // no select on loaded values, so all loads stay in flight
     uint64_t rr[STEPS], rr_next[STEPS];
-    int64_t tf_cur = 0, tf_nxt = 0;
-    if (rs < re) {
-        const int cn0 = (int)(min(rs + (uint32_t)CHUNK, re) - rs);
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s)
+        rr[s] = 0;
+    if (c.avail > 0) {
 #pragma unroll
         for (int s = 0; s < STEPS; ++s)
-            rr[s] = records[rs + min(wave * PER_WAVE + s * kWave + lane, cn0 - 1)];
-        if (fo.nf > 0)
-            tf_cur = fo.t_frames[min(tid, fo.nf - 1)];
+            rr[s] = records[cs + min((uint32_t)(wave * PER_WAVE + s * kWave + lane), c.avail - 1u)];
     }
-    // nothing may be pending on `rr` at the loop head, or the compiler waits
+    int64_t tfv = 0, tfv_next = 0;
+    if (nf > 0)
+        tfv = fo.t_frames[min(tid, nf - 1)];
+    // nothing may be pending on these at the loop head, or the compiler waits
     // there for everything outstanding, frame stores included
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 
-    for (uint32_t cs = rs; cs < re;) {
-        // this chunk: at most CHUNK records, completing at most kFrameGroup
-        // frames (records after the group's last frame wait for the next one)
-        uint32_t ce = min(cs + (uint32_t)CHUNK, re);
-        const int jmax = min(j + kFrameGroup, fo.nf);
-        if (j < fo.nf && jmax < fo.nf)
-            ce = first_record_after(records, cs, ce, t_ref, load_const(fo.t_frames, jmax - 1));
-        const int cn = (int)(ce - cs);
-        const int64_t t_next = (ce < re) ? t_ref + record_dt(load_const(records, ce)) : INT64_MAX;
-        int j_end = (t_next == INT64_MAX) ? jmax
-                                          : min(first_frame_at_or_after(fo.t_frames, j, fo.nf, t_next), jmax);
-        if (cn == 0 && j_end == j)
-            j_end = min(j + 1, fo.nf);  // progress even with unsorted frame times
-        const int nfw = j_end - j;     // frames of this chunk
+    while (cs < re || j < nf) {
+        // ---- chunk and segment bounds (uniform) ----
+        const int jmax0 = min(j + kFrameGroup, nf);
+        int jmax = jmax0;
+        if (jmax > j + 1 && mp.k * (double)(c.tf_hi - c.tb) > kMaxSegmentDecay)
+            jmax = j + 1;
+        const int64_t tf_lim = (jmax < nf) ? (jmax == jmax0 ? c.tf_hi : c.tb) : INT64_MAX;
+        uint32_t cn;
+        if (c.avail == 0)
+            cn = 0;
+        else if (jmax == nf || c.t_last <= tf_lim)
+            cn = c.avail;
+        else
+            cn = first_record_after(records, cs, cs + c.avail, t_ref, tf_lim) - cs;
+        const uint32_t ce = cs + cn;
+        // frames the chunk completes: all of the segment unless the record
+        // after the chunk (t_after) comes before its end
+        const bool search = (cn == c.avail) && (ce < re);
+        const int64_t tb = c.tb;
 
-        // prefetch the next chunk's records and frame times (before this
-        // chunk's frame stores are issued)
-        if (ce < re) {
-            const int cn1 = (int)(min(ce + (uint32_t)CHUNK, re) - ce);
+        // prefetch the next chunk's records (before this chunk's frame stores)
+        const uint32_t avail1 = min((uint32_t)CHUNK, re - ce);
+        if (avail1 > 0) {
 #pragma unroll
             for (int s = 0; s < STEPS; ++s)
-                rr_next[s] = records[ce + min(wave * PER_WAVE + s * kWave + lane, cn1 - 1)];
+                rr_next[s] = records[ce + min((uint32_t)(wave * PER_WAVE + s * kWave + lane), avail1 - 1u)];
         }
-        if (j_end < fo.nf)
-            tf_nxt = fo.t_frames[min(j_end + tid, fo.nf - 1)];
 
+        // the segment's frame times and decay bases; the visible state
+        // before this chunk's events
         if (tid < kFrameGroup) {
-            tfl[tid] = tf_cur;
-            ktl[tid] = mp.k * (double)(tf_cur - t_base);
+            tfl[tid] = tfv;
+            ktl[tid] = mp.k * (double)(tfv - tb);
         }
-        // 2a. stable ranks inside the wave
-        for (int k = lane; k < TILE; k += kWave)
-            cnt[wave][k] = 0;
-        wave_sync();
-        uint32_t rank[STEPS];
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            const int c = wave * PER_WAVE + s * kWave + lane;
-            rank[s] = wave_stable_rank(c < cn, record_lpx(rr[s]) & (TILE - 1), kbits, cnt[wave]);
-        }
-        __syncthreads();
-        // 2b. exclusive scan over (pixel, wave), pixel-major
-        {
-            uint32_t v[PPT][kWavesPerBlock];
-            uint32_t sum = 0;
-#pragma unroll
-            for (int i = 0; i < PPT; ++i)
-#pragma unroll
-                for (int w = 0; w < kWavesPerBlock; ++w) {
-                    v[i][w] = cnt[w][tid * PPT + i];
-                    sum += v[i][w];
-                }
-            uint32_t inc = sum;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
-                if (lane >= o)
-                    inc += n;
-            }
-            if (lane == kWave - 1)
-                scan_w[wave] = inc;
-            __syncthreads();
-            uint32_t run = inc - sum;
-            for (int w = 0; w < wave; ++w)
-                run += scan_w[w];
-#pragma unroll
-            for (int i = 0; i < PPT; ++i)
-#pragma unroll
-                for (int w = 0; w < kWavesPerBlock; ++w) {
-                    cnt[w][tid * PPT + i] = run;
-                    run += v[i][w];
-                }
-        }
-        __syncthreads();
-        // 2c. scatter into pixel order (every index is checked, so that a
-        // broken invariant can only flag an error, never leave the chunk)
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            const int c = wave * PER_WAVE + s * kWave + lane;
-            if (c < cn) {
-                const uint32_t at = cnt[wave][record_lpx(rr[s]) & (TILE - 1)] + rank[s];
-                if (at < (uint32_t)cn)
-                    sorted[at] = rr[s];
-                else
-                    bad = true;
-            }
-        }
-        __syncthreads();
-
-        // 3. phase A: each pixel's events of the chunk in array order; the
-        // change list keeps, per frame index jc of the chunk that first
-        // includes some event, the state after the last such event.  Entries
-        // go over the pixel's own slots of `sorted`/chg_*, behind the read
-        // position.  Events after the chunk's last frame (jc == nfw) make no
-        // entry: the frames of later chunks see the final state.
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-            const int l = tid + i * kBlock;
-            const uint32_t end = min((l + 1 < TILE) ? cnt[0][l + 1] : (uint32_t)cn, (uint32_t)cn);
-            const uint32_t beg = min(cnt[0][l], end);
-            uint32_t w = beg;          // change list write position
-            int jc_prev = -1;
-            for (uint32_t e = beg; e < end; ++e) {
-                const uint64_t r = sorted[e];
-                const int64_t t = t_ref + record_dt(r);
-                apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t, record_pos(r));
-                const int jc = lds_lower_bound(tfl, nfw, t);
-                if (jc < nfw) {
-                    if (jc != jc_prev && jc_prev >= 0)
-                        ++w;           // a new entry; the previous one is final
-                    chg_S[w] = px.S[i];
-                    chg_A[w] = __fma_rn(mp.k, (double)(t - t_base), 1.0);
-                    chg_j[w] = (uint16_t)jc;
-                    jc_prev = jc;
-                }
-            }
-            px.cbase[i] = beg;
-            px.nch[i] = (jc_prev >= 0) ? (w - beg + 1u) : 0u;
-            px.idx[i] = 0;
-            const uint32_t e0 = min(beg, (uint32_t)max(cn - 1, 0));
-            px.jn[i] = px.nch[i] ? (int)chg_j[e0] : 0x7FFFFFFF;
-            px.Sn[i] = chg_S[e0];
-            px.An[i] = chg_A[e0];
-        }
-        // Wait for the prefetched records and frame times now: this also
-        // drains the frame stores of the previous chunk (one counter covers
-        // loads and stores), which have had the whole sort to complete.
-        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        // 4. phase B: the frames this chunk completes
-        walk_frames<PPT, BK, CHUNK>(mp, px, fo, j, j_end, t_base, ktl, chg_S, chg_A, chg_j, q0,
-                                    npix);
-        j = j_end;
-        // the frames of later chunks see every event of this one
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             px.Sf[i] = px.S[i];
-            px.Af[i] = __fma_rn(mp.k, (double)(px.T[i] - t_base), 1.0);
-            px.nch[i] = 0;
-            px.jn[i] = 0x7FFFFFFF;
+            px.Af[i] = __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
         }
+        uint32_t rank[STEPS];
+        if (cn > 0) {
+            // 2a. stable ranks inside the wave
+            for (int k = lane; k < TILE; k += kWave)
+                cnt[wave][k] = 0;
+            wave_sync();
+#pragma unroll
+            for (int s = 0; s < STEPS; ++s) {
+                const uint32_t c_ = (uint32_t)(wave * PER_WAVE + s * kWave + lane);
+                rank[s] = wave_stable_rank(c_ < cn, record_lpx(rr[s]) & (TILE - 1), kbits, cnt[wave]);
+            }
+        }
+        __syncthreads();
+        int j_end = jmax;
+        if (search)
+            j_end = j + frames_before(tfl, jmax - j, c.t_after);
+        if (cn == 0 && j_end == j)
+            j_end = min(j + 1, nf);  // progress even with unsorted frame times
+        const int nfw = j_end - j;
+
+        // prefetch the next segment's frame times and the next chunk's bounds
+        if (j_end < nf)
+            tfv_next = fo.t_frames[min(j_end + tid, nf - 1)];
+        const ChunkCtl c1 = chunk_ctl<CHUNK>(records, ce, re, t_ref, fo, j_end);
+
+        if (cn > 0) {
+            // 2b. the segment frame of each record, kept with its rank
+#pragma unroll
+            for (int s = 0; s < STEPS; ++s) {
+                const int jc = frames_before(tfl, nfw, t_ref + record_dt(rr[s]));
+                rank[s] |= (uint32_t)jc << 16;
+            }
+            // 2c. exclusive scan over (pixel, wave), pixel-major
+            {
+                uint32_t v[PPT][kWavesPerBlock];
+                uint32_t sum = 0;
+#pragma unroll
+                for (int i = 0; i < PPT; ++i)
+#pragma unroll
+                    for (int w = 0; w < kWavesPerBlock; ++w) {
+                        v[i][w] = cnt[w][tid * PPT + i];
+                        sum += v[i][w];
+                    }
+                uint32_t inc = sum;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
+                    if (lane >= o)
+                        inc += n;
+                }
+                if (lane == kWave - 1)
+                    scan_w[wave] = inc;
+                __syncthreads();
+                uint32_t run = inc - sum;
+                for (int w = 0; w < wave; ++w)
+                    run += scan_w[w];
+#pragma unroll
+                for (int i = 0; i < PPT; ++i)
+#pragma unroll
+                    for (int w = 0; w < kWavesPerBlock; ++w) {
+                        cnt[w][tid * PPT + i] = (uint16_t)run;
+                        run += v[i][w];
+                    }
+            }
+            __syncthreads();
+            // 2d. scatter into pixel order, the frame index over the pixel
+            // field (every index is checked, so that a broken invariant can
+            // only flag an error, never leave the chunk)
+#pragma unroll
+            for (int s = 0; s < STEPS; ++s) {
+                const uint32_t c_ = (uint32_t)(wave * PER_WAVE + s * kWave + lane);
+                if (c_ < cn) {
+                    const uint32_t at = (uint32_t)cnt[wave][record_lpx(rr[s]) & (TILE - 1)] + (rank[s] & 0xFFFFu);
+                    if (at < cn)
+                        sorted[at] = (rr[s] & ~kLpxMask) | ((uint64_t)(rank[s] >> 16) << 48);
+                    else
+                        bad = true;
+                }
+            }
+            __syncthreads();
+
+            // 3. phase A: each pixel's events of the chunk in array order; the
+            // change list keeps, per segment frame jc that first includes
+            // some event, the state after the last such event.  Entries go
+            // over the pixel's own slots of `sorted`/chg_*, behind the read
+            // position.  Events after the segment (jc == nfw) make no entry.
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int l = tid + i * kBlock;
+                const uint32_t end = min((l + 1 < TILE) ? (uint32_t)cnt[0][l + 1] : cn, cn);
+                const uint32_t beg = min((uint32_t)cnt[0][l], end);
+                uint32_t w = beg;
+                int jc_prev = -1;
+                for (uint32_t e = beg; e < end; ++e) {
+                    const uint64_t r = sorted[e];
+                    const int64_t t = t_ref + record_dt(r);
+                    apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t, record_pos(r));
+                    const int jc = (int)record_lpx(r);
+                    if (jc < nfw) {
+                        if (jc != jc_prev && jc_prev >= 0)
+                            ++w;  // a new entry; the previous one is final
+                        chg_S[w] = px.S[i];
+                        chg_A[w] = __fma_rn(mp.k, (double)(t - tb), 1.0);
+                        chg_j[w] = (uint16_t)jc;
+                        jc_prev = jc;
+                    }
+                }
+                px.nx[i] = beg;
+                px.cend[i] = (jc_prev >= 0) ? w + 1u : beg;
+                load_change<PPT, CHUNK>(px, i, chg_S, chg_A, chg_j, px.jn[i], px.Sn[i], px.An[i]);
+                load_change<PPT, CHUNK>(px, i, chg_S, chg_A, chg_j, px.jn2[i], px.Sn2[i], px.An2[i]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                px.jn[i] = kNever;
+                px.jn2[i] = kNever;
+            }
+        }
+
+        // Wait for the prefetched records and frame times now: this also
+        // drains the frame stores of the previous segment (one counter covers
+        // loads and stores), which have had the whole sort to complete.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        // 4. phase B: the frames this chunk completes
+        if (nfw > 0) {
+            const size_t base = (size_t)j * (size_t)npix + (size_t)tile * TILE;
+            walk_dispatch<PPT, BK, CHUNK>(mode, mp, px, nfw, ktl, chg_S, chg_A, chg_j,
+                                          fo.frames ? fo.frames + base : nullptr,
+                                          fo.frames_u8 ? fo.frames_u8 + base : nullptr, npix, off, in);
+        }
+        j = j_end;
+        cs = ce;
+        c = c1;
 #pragma unroll
         for (int s = 0; s < STEPS; ++s)
             rr[s] = rr_next[s];
-        tf_cur = tf_nxt;
-        cs = ce;
+        tfv = tfv_next;
         __syncthreads();  // LDS is reused by the next chunk
     }
-    // frames after the last event (no change lists: nch = 0, jn never hit)
-    walk_frames<PPT, BK, CHUNK>(mp, px, fo, j, fo.nf, t_base, nullptr, chg_S, chg_A, chg_j, q0,
-                                npix);
 
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int64_t q = q0 + (int64_t)i * kBlock;
-        if (q < npix) {
+        if (in[i]) {
             const float hi = (float)px.S[i];
             st.S_hi[q] = hi;
             st.S_lo[q] = (float)(px.S[i] - (double)hi);
@@ -427,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
     // frame times must be non-decreasing; the first workgroup checks
     if (tile == 0) {
         bool unsorted = false;
-        for (int jj = 1 + tid; jj < fo.nf; jj += kBlock)
+        for (int jj = 1 + tid; jj < nf; jj += kBlock)
             unsorted |= fo.t_frames[jj] < fo.t_frames[jj - 1];
         if (unsorted)
             atomicOr(&diag->flags, 2u);  // ESI_DIAG_FRAMES_UNSORTED

@@ -25,6 +25,7 @@ struct esi_state {
     // scratch of integrate calls, grown on demand
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    int bucket_slots = 1024;  // bucketing workgroups resident at once
     bool poisoned = false;
     uint64_t calls = 0;
     // profiling: HIP events around the two phases of recorded calls
@@ -70,8 +71,9 @@ MethodParams method_params(const esi_params& p)
 }
 
 // The split of one call into tiles and bucketing units: the smallest tile
-// (most workgroups) with at most kMaxTiles tiles; units of 2^kUnitLog events.
-Schedule make_schedule(int64_t npix, int64_t n)
+// (most workgroups) with at most kMaxTiles tiles; the events split evenly over
+// as many bucketing workgroups as the GPU holds at once (`slots`).
+Schedule make_schedule(int64_t npix, int64_t n, int slots)
 {
     Schedule s{};
     for (int ppt = 1; ppt <= 8; ppt *= 2) {
@@ -81,9 +83,9 @@ Schedule make_schedule(int64_t npix, int64_t n)
         if (s.ntiles <= kMaxTiles)
             break;
     }
-    s.chunk = kChunk;
-    s.unit_log = kUnitLog;
-    s.nunits = (n + ((int64_t)1 << kUnitLog) - 1) >> kUnitLog;
+    const int64_t per = (n + slots - 1) / std::max(slots, 1);
+    s.unit_events = std::max<int64_t>(256, (per + 255) / 256 * 256);
+    s.nunits = (n + s.unit_events - 1) / s.unit_events;
     return s;
 }
 
@@ -175,6 +177,7 @@ esi_status esi_create_state(int32_t width, int32_t height, const esi_params* par
     st->dev.H = height;
     st->dev.npix = npix;
     st->diag = (DiagDev*)(base + o_diag);
+    st->bucket_slots = bucket_slots(make_schedule(npix, 0, 1).ntiles);
     if (launch_reset(st->dev, params->t0_us, st->diag, stream) != hipSuccess) {
         (void)hipFree(st->state_mem);
         delete st;
@@ -280,15 +283,15 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
     DeviceGuard g(st->device);
     const int64_t n = (int64_t)ev->n;
     const MethodParams mp = method_params(st->params);
-    const Schedule sc = make_schedule(st->npix, n);
+    const Schedule sc = make_schedule(st->npix, n, st->bucket_slots);
     EventsDev evd{ev->x, ev->y, ev->t, ev->p, n};
     CallScratch cs{};
     if (n > 0) {
         const int64_t M = (int64_t)sc.ntiles * sc.nunits;
-        const int seg = scan_segment_units(sc.nunits);
-        const int64_t nseg = (sc.nunits + seg - 1) / seg;
+        const int64_t nseg = (int64_t)scan_segments(sc.nunits);
         const size_t o_bs = align_up(4 * (size_t)M, 256);
-        const size_t o_tot = o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
+        const size_t o_tt = o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
+        const size_t o_tot = o_tt + align_up(4 * (size_t)sc.ntiles, 256);
         const size_t o_rec = o_tot + 256;
         const size_t need = o_rec + 8 * (size_t)n;
         if (need > st->scratch_bytes) {
@@ -309,6 +312,7 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
         char* base = (char*)st->scratch;
         cs.table = (uint32_t*)base;
         cs.blocksum = (uint32_t*)(base + o_bs);
+        cs.tile_tot = (uint32_t*)(base + o_tt);
         cs.total = (uint32_t*)(base + o_tot);
         cs.records = (uint64_t*)(base + o_rec);
     }

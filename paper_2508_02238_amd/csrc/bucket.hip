@@ -6,28 +6,34 @@
 // consecutive pixels) while keeping array order inside every tile (and so
 // inside every pixel): a counting sort whose ranks are stable.
 //
-//   k_hist      one workgroup per unit of 2^unit_log consecutive events:
-//               per-tile counts of the unit's valid events -> table[unit][tile];
-//               out-of-range events are counted as dropped.
-//   k_seg_sum,  exclusive scan of the table in (tile, unit) order, done
-//   k_seg_scan, column-wise so every access is a coalesced row access:
-//   k_seg_down  per-tile sums over segments of units, a scan over segments
-//               and tiles, then a rescan of each segment writing offsets.
-//   k_bucket    one workgroup per unit again: each wave ranks its quarter of
-//               the unit stably by tile (wave-wide key match), a scan over
-//               (tile, wave) gives every event its place in the unit sorted
-//               by tile, the 64-bit records (time offset, pixel in tile,
-//               polarity) are staged in LDS in that order, and each tile's run
-//               is then written to its bucket in one burst.  Also flags
-//               decreasing times and calls whose span the record cannot hold.
+// The stream is split into G equal ranges of events, one per workgroup, with
+// G = the number of bucketing workgroups the GPU holds at once, so every
+// range is processed in a single round with no tail of late workgroups.
 //
-// Workgroups are dispatched round-robin over the 8 XCDs; units are assigned
-// so that the workgroups of one XCD take consecutive units.  Consecutive
-// units write adjacent runs of every tile bucket within a short time, so the
+//   k_hist      per range: per-tile counts of its valid events ->
+//               table[range][tile]; out-of-range events are counted as dropped.
+//   k_seg_sum,  exclusive scan of the table in (tile, range) order, done
+//   k_seg_down  column-wise so every access is a coalesced row access:
+//               per-tile sums over segments of ranges (and per-tile totals),
+//               then each segment rescanned into offsets.
+//   k_bucket    per range again, in sub-batches of SUB events: each wave ranks
+//               its quarter of the sub-batch stably by tile (wave-wide key
+//               match), a scan over (tile, wave) gives every event its place
+//               in the sub-batch sorted by tile, the 64-bit records (time
+//               offset, pixel in tile, polarity) are staged in LDS in that
+//               order, and each tile's run is appended to its bucket.  Also
+//               flags decreasing times and calls whose span the record cannot
+//               hold.
+//
+// Workgroups are dispatched round-robin over the 8 XCDs; ranges are assigned
+// so that the workgroups of one XCD take consecutive ranges.  Neighbouring
+// ranges append adjacent runs to every tile bucket within a short time, so the
 // cache lines of a bucket are completed in one XCD's L2 before they are
 // written back (scattered 8-byte stores spread over the whole kernel would
 // reach HBM as partial lines).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "esi_internal.hpp"
 
@@ -35,6 +41,8 @@ namespace esi {
 namespace {
 
 constexpr int kXcds = 8;
+constexpr int kSegRows = 16;  // table rows (ranges) per segment of the column scan
+constexpr int kSub = 2048;    // events per sub-batch of k_bucket
 
 // Bijection blockIdx -> work index that gives each XCD a contiguous range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
@@ -50,18 +58,24 @@ __device__ __forceinline__ bool valid_q(uint32_t x, uint32_t y, int W, int H, ui
     return x < (uint32_t)W && y < (uint32_t)H;
 }
 
+// Range `unit` holds events [unit E, min((unit + 1) E, n)); E is a multiple
+// of kBlock.
+// Workgroup 0 also clears the per-tile totals that k_seg_sum accumulates.
 __global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int tile_log, int K,
-                                                 int unit_log, int64_t B, uint32_t* table,
+                                                 int64_t E, uint32_t* table, uint32_t* tile_tot,
                                                  DiagDev* diag)
 {
     extern __shared__ uint32_t h[];
     const int64_t unit = xcd_block(blockIdx.x, gridDim.x);
-    for (int k = threadIdx.x; k < K; k += kBlock)
+    for (int k = threadIdx.x; k < K; k += kBlock) {
         h[k] = 0;
+        if (blockIdx.x == 0)
+            tile_tot[k] = 0;
+    }
     __syncthreads();
     uint32_t drop = 0;
-    const int64_t lo = unit << unit_log;
-    const int64_t hi = min(lo + ((int64_t)1 << unit_log), ev.n);
+    const int64_t lo = unit * E;
+    const int64_t hi = min(lo + E, ev.n);
     const bool vec = (((uintptr_t)ev.x | (uintptr_t)ev.y) & 15u) == 0;
     int64_t i = lo;
     if (vec) {
@@ -102,49 +116,51 @@ __global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int
 }
 
 // ---- exclusive scan of table[u][k] in (k, u) order, column-wise -------------
-// Segments of `seg` units.  segsum[s][k] = sum over the units of segment s.
+// Segments of kSegRows rows.  k_seg_sum: segsum[s][k] = sum over the rows of
+// segment s, and tile_tot[k] += that sum.  k_seg_down: the offset of
+// (unit u, tile k) = (tiles before k) + (segments before u's) + (rows of u's
+// segment before u), written over table[u][k].
 
 __global__ __launch_bounds__(kBlock) void k_seg_sum(const uint32_t* table, int K, int64_t B,
-                                                    int seg, uint32_t* segsum)
+                                                    uint32_t* segsum, uint32_t* tile_tot)
 {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     const int s = blockIdx.y;
     if (k >= K)
         return;
-    const int64_t u0 = (int64_t)s * seg, u1 = min(u0 + seg, B);
+    const int64_t u0 = (int64_t)s * kSegRows;
+    uint32_t v[kSegRows];
+#pragma unroll
+    for (int r = 0; r < kSegRows; ++r)  // all loads in flight at once
+        v[r] = (u0 + r < B) ? table[(u0 + r) * K + k] : 0u;
     uint32_t sum = 0;
-    for (int64_t u = u0; u < u1; ++u)
-        sum += table[u * K + k];
+#pragma unroll
+    for (int r = 0; r < kSegRows; ++r)
+        sum += v[r];
     segsum[(int64_t)s * K + k] = sum;
+    if (sum)
+        atomicAdd(&tile_tot[k], sum);
 }
 
-// One workgroup: per tile, exclusive scan over segments; then the exclusive
-// scan of tile totals gives each tile's start.  segsum[s][k] becomes the
-// offset of (segment s, tile k) in the whole (tile, unit) order.  Each thread
-// owns up to 4 consecutive tiles (K <= 4096).
-__global__ __launch_bounds__(1024) void k_seg_scan(uint32_t* segsum, int K, int nseg,
-                                                   uint32_t* total, DiagDev* diag)
+__global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int64_t B,
+                                                     const uint32_t* segsum,
+                                                     const uint32_t* tile_tot, uint32_t* total,
+                                                     DiagDev* diag)
 {
-    __shared__ uint32_t sw[1024 / kWave];
-    const int per = (K + 1023) / 1024;
-    const int k0 = threadIdx.x * per;
-    uint32_t tot[4] = {0u, 0u, 0u, 0u};
-    uint32_t mine = 0;
-    for (int kk = 0; kk < per && kk < 4; ++kk) {
-        const int k = k0 + kk;
-        if (k >= K)
-            break;
-        uint32_t run = 0;
-        for (int s = 0; s < nseg; ++s) {
-            const uint32_t v = segsum[(int64_t)s * K + k];
-            segsum[(int64_t)s * K + k] = run;
-            run += v;
-        }
-        tot[kk] = run;
-        mine += run;
+    constexpr int kBatch = 16;
+    constexpr int kPer = (kMaxTiles + kBlock - 1) / kBlock;  // tile totals per thread
+    __shared__ uint32_t base[kMaxTiles];
+    __shared__ uint32_t sw[kWavesPerBlock];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    // exclusive scan of the tile totals (each workgroup for itself)
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int k = tid * kPer + i;
+        v[i] = (k < K) ? tile_tot[k] : 0u;
+        sum += v[i];
     }
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    uint32_t inc = mine;
+    uint32_t inc = sum;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
         const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
@@ -154,58 +170,70 @@ __global__ __launch_bounds__(1024) void k_seg_scan(uint32_t* segsum, int K, int 
     if (lane == kWave - 1)
         sw[wave] = inc;
     __syncthreads();
-    uint32_t base = inc - mine, all = 0;
-    for (int w = 0; w < 1024 / kWave; ++w) {
-        base += (w < wave) ? sw[w] : 0u;
+    uint32_t run = inc - sum, all = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+        run += (w < wave) ? sw[w] : 0u;
         all += sw[w];
     }
-    for (int kk = 0; kk < per && kk < 4; ++kk) {
-        const int k = k0 + kk;
-        if (k >= K)
-            break;
-        for (int s = 0; s < nseg; ++s)
-            segsum[(int64_t)s * K + k] += base;
-        base += tot[kk];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int k = tid * kPer + i;
+        if (k < K)
+            base[k] = run;
+        run += v[i];
     }
-    if (threadIdx.x == 0) {
+    __syncthreads();
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
         *total = all;
         atomicAdd(&diag->accepted, (unsigned long long)all);
     }
-}
 
-__global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int64_t B, int seg,
-                                                     const uint32_t* segsum)
-{
-    const int k = blockIdx.x * kBlock + threadIdx.x;
+    const int k = blockIdx.x * kBlock + tid;
     const int s = blockIdx.y;
     if (k >= K)
         return;
-    const int64_t u0 = (int64_t)s * seg, u1 = min(u0 + seg, B);
-    uint32_t run = segsum[(int64_t)s * K + k];
-    for (int64_t u = u0; u < u1; ++u) {
-        const uint32_t c = table[u * K + k];
-        table[u * K + k] = run;
-        run += c;
+    // segments before this one, loads in batches
+    uint32_t off = base[k];
+    for (int s0 = 0; s0 < s; s0 += kBatch) {
+        uint32_t w[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+            w[b] = (s0 + b < s) ? segsum[(int64_t)(s0 + b) * K + k] : 0u;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+            off += w[b];
+    }
+    const int64_t u0 = (int64_t)s * kSegRows;
+    uint32_t c[kSegRows];
+#pragma unroll
+    for (int r = 0; r < kSegRows; ++r)
+        c[r] = (u0 + r < B) ? table[(u0 + r) * K + k] : 0u;
+#pragma unroll
+    for (int r = 0; r < kSegRows; ++r) {
+        if (u0 + r < B)
+            table[(u0 + r) * K + k] = off;
+        off += c[r];
     }
 }
 
 // ---- stable bucketing, staged in LDS ------------------------------------------
 
-template <int UNIT_LOG>
-__global__ __launch_bounds__(kBlock) void k_bucket(EventsDev ev, int W, int H, int tile_log,
-                                                   int K, int64_t B, const uint32_t* table,
+template <int SUB>
+__global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H, int tile_log,
+                                                   int K, int64_t E, const uint32_t* table,
                                                    uint64_t* records, int64_t cap, DiagDev* diag)
 {
-    constexpr int U = 1 << UNIT_LOG;              // events per unit (workgroup)
-    constexpr int PER_WAVE = U / kWavesPerBlock;  // events per wave
-    constexpr int STEPS = PER_WAVE / kWave;       // steps of 64 per wave
-    constexpr int BATCH = 8;                      // steps loaded ahead
-    static_assert(STEPS % BATCH == 0, "unit size");
+    constexpr int PER_WAVE = SUB / kWavesPerBlock;  // events per wave per sub-batch
+    constexpr int STEPS = PER_WAVE / kWave;         // steps of 64 per wave
+    constexpr int BATCH = STEPS < 8 ? STEPS : 8;    // steps loaded ahead
+    static_assert(STEPS % BATCH == 0, "sub-batch size");
     extern __shared__ uint64_t smem[];
-    uint64_t* staged = smem;                                   // [U]
-    uint32_t* gbase = (uint32_t*)(staged + U);                 // [K] bucket offset of this unit
-    uint16_t* cw = (uint16_t*)(gbase + K);                     // [4][K] per-wave counters
-    uint16_t* skey = cw + kWavesPerBlock * K;                  // [U] tile of each staged record
+    uint64_t* staged = smem;                      // [SUB] records of the sub-batch by tile
+    uint32_t* gbase = (uint32_t*)(staged + SUB);  // [K] next bucket position of each tile
+    uint16_t* cw = (uint16_t*)(gbase + K);        // [4][K] per-wave counters, then run starts
+    uint16_t* skey = cw + kWavesPerBlock * K;     // [SUB] tile of each staged record
+    __shared__ uint32_t scan_w[kWavesPerBlock];
+    __shared__ uint32_t sub_total;
 
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
@@ -214,128 +242,140 @@ __global__ __launch_bounds__(kBlock) void k_bucket(EventsDev ev, int W, int H, i
     const uint32_t* row = table + unit * K;
     for (int k = tid; k < K; k += kBlock)
         gbase[k] = row[k];
-    for (int k = tid; k < kWavesPerBlock * K; k += kBlock)
-        cw[k] = 0;
-    __syncthreads();
 
     const uint32_t tmask = (1u << tile_log) - 1u;
     const int kbits = key_bits_for((uint32_t)K);
     const int64_t t_ref = ev.t[0];
-    const int64_t lo = (unit << UNIT_LOG) + (int64_t)wave * PER_WAVE;
-    const int64_t hi = min((unit << UNIT_LOG) + U, ev.n);
-    int64_t t_carry = (lo > 0 && lo - 1 < ev.n) ? ev.t[lo - 1] : INT64_MIN;
-    uint32_t flags = 0;
-    uint64_t recs[STEPS];
-    uint32_t packed[STEPS];  // rank | tile << 16, or ~0 for no event
+    const int64_t u_lo = unit * E;
+    const int64_t u_hi = min(u_lo + E, ev.n);
     uint16_t* mycw = cw + wave * K;
-#pragma unroll
-    for (int b0 = 0; b0 < STEPS; b0 += BATCH) {
-        uint32_t xs[BATCH], ys[BATCH];
-        int64_t ts[BATCH];
-        int ps[BATCH];
-#pragma unroll
-        for (int s = 0; s < BATCH; ++s) {
-            // clamped index, no select on the loaded values: all loads of the
-            // batch stay in flight together
-            const int64_t i = max(min(lo + (b0 + s) * kWave + lane, hi - 1), (int64_t)0);
-            xs[s] = ev.x[i];
-            ys[s] = ev.y[i];
-            ts[s] = ev.t[i];
-            ps[s] = ev.p[i];
-        }
-#pragma unroll
-        for (int s = 0; s < BATCH; ++s) {
-            const int64_t i = lo + (b0 + s) * kWave + lane;
-            const bool in = i < hi;
-            uint32_t q;
-            const bool ok = in && valid_q(xs[s], ys[s], W, H, q);
-            const int64_t t = ts[s];
-            // decreasing time versus the previous event in array order
-            int64_t tprev = __shfl_up(t, 1);
-            if (lane == 0)
-                tprev = t_carry;
-            if (in && t < tprev)
-                flags |= 1u;  // ESI_DIAG_UNSORTED
-            t_carry = __shfl(t, kWave - 1);
-            const int64_t dt = t - t_ref;
-            if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
-                flags |= 4u;  // ESI_DIAG_TIME_RANGE
-            const uint32_t key = ok ? (q >> tile_log) : 0u;
-            const uint32_t rank = wave_stable_rank(ok, key, kbits, mycw);
-            packed[b0 + s] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
-            recs[b0 + s] = pack_record(dt, q & tmask, ps[s] > 0);
-        }
-    }
-    __syncthreads();
-
-    // exclusive scan over (tile, wave), tile-major: start of each wave's run
-    // of each tile inside the unit sorted by tile
-    __shared__ uint32_t scan_w[kWavesPerBlock];
-    __shared__ uint32_t unit_total;
-    {
-        const int kpt = (K + kBlock - 1) / kBlock;  // tiles per thread, consecutive
-        const int k0 = tid * kpt;
-        uint32_t sum = 0;
-        for (int kk = 0; kk < kpt; ++kk) {
-            const int k = k0 + kk;
-            if (k < K)
-                for (int w = 0; w < kWavesPerBlock; ++w)
-                    sum += cw[w * K + k];
-        }
-        uint32_t inc = sum;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
-            if (lane >= o)
-                inc += n;
-        }
-        if (lane == kWave - 1)
-            scan_w[wave] = inc;
-        __syncthreads();
-        uint32_t run = inc - sum;
-        for (int w = 0; w < wave; ++w)
-            run += scan_w[w];
-        if (tid == kBlock - 1)
-            unit_total = run + sum;
-        for (int kk = 0; kk < kpt; ++kk) {
-            const int k = k0 + kk;
-            if (k < K)
-                for (int w = 0; w < kWavesPerBlock; ++w) {
-                    const uint32_t c = cw[w * K + k];
-                    cw[w * K + k] = (uint16_t)run;
-                    run += c;
-                }
-        }
-    }
-    __syncthreads();
-
-    // stage the records in tile order
+    uint32_t flags = 0;
     bool bad = false;
+
+    for (int64_t sb = u_lo; sb < u_hi; sb += SUB) {
+        // each wave clears its own counters
+        for (int k = lane; k < K; k += kWave)
+            mycw[k] = 0;
+        wave_sync();
+        const int64_t lo = sb + (int64_t)wave * PER_WAVE;
+        const int64_t hi = min(sb + SUB, u_hi);
+        int64_t t_carry = (lo > 0 && lo - 1 < ev.n) ? ev.t[lo - 1] : INT64_MIN;
+        uint64_t recs[STEPS];
+        uint32_t packed[STEPS];  // rank | tile << 16, or ~0 for no event
 #pragma unroll
-    for (int s = 0; s < STEPS; ++s) {
-        if (packed[s] != 0xFFFFFFFFu) {
-            const uint32_t key = packed[s] >> 16;
-            const uint32_t pos = (uint32_t)mycw[key] + (packed[s] & 0xFFFFu);
-            if (pos < (uint32_t)U) {
-                staged[pos] = recs[s];
-                skey[pos] = (uint16_t)key;
-            } else {
-                bad = true;
+        for (int b0 = 0; b0 < STEPS; b0 += BATCH) {
+            uint32_t xs[BATCH], ys[BATCH];
+            int64_t ts[BATCH];
+            int ps[BATCH];
+#pragma unroll
+            for (int s = 0; s < BATCH; ++s) {
+                // clamped index, no select on the loaded values: all loads of
+                // the batch stay in flight together
+                const int64_t i = max(min(lo + (b0 + s) * kWave + lane, hi - 1), (int64_t)0);
+                xs[s] = ev.x[i];
+                ys[s] = ev.y[i];
+                ts[s] = ev.t[i];
+                ps[s] = ev.p[i];
+            }
+#pragma unroll
+            for (int s = 0; s < BATCH; ++s) {
+                const int64_t i = lo + (b0 + s) * kWave + lane;
+                const bool in = i < hi;
+                uint32_t q = 0;
+                const bool ok = in && valid_q(xs[s], ys[s], W, H, q);
+                const int64_t t = ts[s];
+                // decreasing time versus the previous event in array order
+                int64_t tprev = __shfl_up(t, 1);
+                if (lane == 0)
+                    tprev = t_carry;
+                if (in && t < tprev)
+                    flags |= 1u;  // ESI_DIAG_UNSORTED
+                t_carry = __shfl(t, kWave - 1);
+                const int64_t dt = t - t_ref;
+                if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
+                    flags |= 4u;  // ESI_DIAG_TIME_RANGE
+                const uint32_t key = ok ? (q >> tile_log) : 0u;
+                const uint32_t rank = wave_stable_rank(ok, key, kbits, mycw);
+                packed[b0 + s] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
+                recs[b0 + s] = pack_record(dt, q & tmask, ps[s] > 0);
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // each tile's run of this unit goes to its bucket: consecutive staged
-    // records of one tile land on consecutive addresses
-    const uint32_t total = min(unit_total, (uint32_t)U);
-    for (uint32_t p = tid; p < total; p += kBlock) {
-        const uint32_t k = skey[p];
-        const int64_t g = (int64_t)gbase[k] + (int64_t)(p - cw[k]);
-        if (k < (uint32_t)K && g >= 0 && g < cap)
-            records[g] = staged[p];
-        else
-            bad = true;
+        // exclusive scan over (tile, wave), tile-major: start of each wave's
+        // run of each tile inside the sub-batch sorted by tile
+        {
+            const int kpt = (K + kBlock - 1) / kBlock;  // tiles per thread, consecutive
+            const int k0 = tid * kpt;
+            uint32_t sum = 0;
+            for (int kk = 0; kk < kpt; ++kk) {
+                const int k = k0 + kk;
+                if (k < K)
+                    for (int w = 0; w < kWavesPerBlock; ++w)
+                        sum += cw[w * K + k];
+            }
+            uint32_t inc = sum;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
+                if (lane >= o)
+                    inc += n;
+            }
+            if (lane == kWave - 1)
+                scan_w[wave] = inc;
+            __syncthreads();
+            uint32_t run = inc - sum;
+            for (int w = 0; w < wave; ++w)
+                run += scan_w[w];
+            if (tid == kBlock - 1)
+                sub_total = run + sum;
+            for (int kk = 0; kk < kpt; ++kk) {
+                const int k = k0 + kk;
+                if (k < K)
+                    for (int w = 0; w < kWavesPerBlock; ++w) {
+                        const uint32_t c = cw[w * K + k];
+                        cw[w * K + k] = (uint16_t)run;
+                        run += c;
+                    }
+            }
+        }
+        __syncthreads();
+
+        // stage the records in tile order
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            if (packed[s] != 0xFFFFFFFFu) {
+                const uint32_t key = packed[s] >> 16;
+                const uint32_t pos = (uint32_t)mycw[key] + (packed[s] & 0xFFFFu);
+                if (pos < (uint32_t)SUB) {
+                    staged[pos] = recs[s];
+                    skey[pos] = (uint16_t)key;
+                } else {
+                    bad = true;
+                }
+            }
+        }
+        __syncthreads();
+
+        // each tile's run of this sub-batch is appended to its bucket:
+        // consecutive staged records of one tile land on consecutive addresses
+        const uint32_t total = min(sub_total, (uint32_t)SUB);
+        for (uint32_t p = tid; p < total; p += kBlock) {
+            const uint32_t k = skey[p];
+            const int64_t g = (int64_t)gbase[k] + (int64_t)(p - cw[k]);
+            if (k < (uint32_t)K && g >= 0 && g < cap)
+                records[g] = staged[p];
+            else
+                bad = true;
+        }
+        __syncthreads();
+        // advance each tile's bucket position by its run length
+        for (int k = tid; k < K; k += kBlock) {
+            const uint32_t p0 = cw[k];
+            const uint32_t p1 = (k + 1 < K) ? (uint32_t)cw[k + 1] : total;
+            gbase[k] += (p1 > p0) ? p1 - p0 : 0u;
+        }
+        __syncthreads();  // staged and cw are reused by the next sub-batch
     }
     if (bad)
         flags |= 8u;  // ESI_DIAG_INTERNAL: never expected
@@ -349,41 +389,44 @@ __global__ __launch_bounds__(kBlock) void k_bucket(EventsDev ev, int W, int H, i
     }
 }
 
+size_t bucket_lds(int K)
+{
+    return sizeof(uint64_t) * kSub + sizeof(uint32_t) * K +
+           sizeof(uint16_t) * (kWavesPerBlock * K + kSub);
+}
+
 }  // namespace
 
-int scan_segment_units(int64_t B)
+int bucket_slots(int K)
 {
-    int64_t seg = 64;
-    while ((B + seg - 1) / seg > 64)
-        seg *= 2;
-    return (int)seg;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket<kSub>, kBlock,
+                                                     bucket_lds(K)) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    return std::max(1, cus) * std::max(1, per_cu);
 }
 
-size_t bucket_lds_bytes(int K)
-{
-    return sizeof(uint64_t) * ((size_t)1 << kUnitLog) + sizeof(uint32_t) * K +
-           sizeof(uint16_t) * (kWavesPerBlock * K + ((size_t)1 << kUnitLog));
-}
+size_t scan_segments(int64_t B) { return (size_t)((B + kSegRows - 1) / kSegRows); }
 
 hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                          const CallScratch& cs, DiagDev* diag, hipStream_t stream)
 {
     const int K = sc.ntiles;
     const int64_t B = sc.nunits;
-    const size_t lds_hist = sizeof(uint32_t) * K;
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)B), dim3(kBlock), lds_hist, stream, ev, st.W, st.H,
-                       sc.tile_log, K, sc.unit_log, B, cs.table, diag);
-    const int seg = scan_segment_units(B);
-    const int nseg = (int)((B + seg - 1) / seg);
+    const int nseg = (int)scan_segments(B);
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)B), dim3(kBlock), sizeof(uint32_t) * K, stream, ev,
+                       st.W, st.H, sc.tile_log, K, sc.unit_events, cs.table, cs.tile_tot, diag);
     const dim3 grid((unsigned)((K + kBlock - 1) / kBlock), (unsigned)nseg);
-    hipLaunchKernelGGL(k_seg_sum, grid, dim3(kBlock), 0, stream, cs.table, K, B, seg, cs.blocksum);
-    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, stream, cs.blocksum, K, nseg, cs.total,
-                       diag);
-    hipLaunchKernelGGL(k_seg_down, grid, dim3(kBlock), 0, stream, cs.table, K, B, seg,
-                       cs.blocksum);
-    hipLaunchKernelGGL(k_bucket<kUnitLog>, dim3((unsigned)B), dim3(kBlock), bucket_lds_bytes(K),
-                       stream, ev, st.W, st.H, sc.tile_log, K, B, cs.table, cs.records, ev.n,
-                       diag);
+    hipLaunchKernelGGL(k_seg_sum, grid, dim3(kBlock), 0, stream, cs.table, K, B, cs.blocksum,
+                       cs.tile_tot);
+    hipLaunchKernelGGL(k_seg_down, grid, dim3(kBlock), 0, stream, cs.table, K, B, cs.blocksum,
+                       cs.tile_tot, cs.total, diag);
+    hipLaunchKernelGGL(k_bucket<kSub>, dim3((unsigned)B), dim3(kBlock), bucket_lds(K), stream, ev,
+                       st.W, st.H, sc.tile_log, K, sc.unit_events, cs.table, cs.records, ev.n, diag);
     return hipGetLastError();
 }
 

@@ -11,19 +11,17 @@ namespace esi {
 // How one integrate call is split into work.
 //   tile   = 256 * ppt consecutive pixels (row-major q), one workgroup each in
 //            the integration kernel;
-//   unit   = 2^unit_log consecutive events, one workgroup each when bucketing.
+//   unit   = unit_events consecutive events (a multiple of 256), one
+//            workgroup each when bucketing.
 struct Schedule {
-    int ppt;          // pixels per thread in the integration kernel: 1, 2, 4, 8
-    int tile_log;     // log2(256 * ppt)
-    int ntiles;       // K = ceil(P / tile)
-    int unit_log;     // log2(events per unit)
-    int64_t nunits;   // B = ceil(n / unit)
-    int chunk;        // records staged in LDS at a time by the integration kernel
+    int ppt;              // pixels per thread in the integration kernel: 1, 2, 4, 8
+    int tile_log;         // log2(256 * ppt)
+    int ntiles;           // K = ceil(P / tile)
+    int64_t unit_events;  // E
+    int64_t nunits;       // B = ceil(n / E)
 };
 
-constexpr int kMaxTiles = 2000;               // bucketing LDS (staging + tables) fits in 64 KB
-constexpr int kUnitLog = 12;                  // events per bucketing unit (workgroup): 4096
-constexpr int kChunk = 1792;
+constexpr int kMaxTiles = 2000;  // bucketing LDS (staging + counters) stays near 32 KB
 
 struct DiagDev {
     unsigned long long dropped;
@@ -35,7 +33,8 @@ struct DiagDev {
 // Scratch of one integrate call (device).
 struct CallScratch {
     uint32_t* table;      // [B][K]: counts, then exclusive offsets in (tile, unit) order
-    uint32_t* blocksum;   // [nseg][K]: per-segment sums, then offsets
+    uint32_t* blocksum;   // [nseg][K]: per-segment sums
+    uint32_t* tile_tot;   // [K]: events per tile
     uint32_t* total;      // [1]: number of accepted events
     uint64_t* records;    // [n]
 };
@@ -58,10 +57,10 @@ struct StateDev {
     int64_t npix;
 };
 
-// Units per segment of the column-wise table scan (at most 64 segments).
-int scan_segment_units(int64_t B);
-// LDS bytes of the bucketing kernel for K tiles.
-size_t bucket_lds_bytes(int K);
+// Bucketing workgroups the current device holds at once for K tiles.
+int bucket_slots(int K);
+// Segments of the column-wise table scan for B units.
+size_t scan_segments(int64_t B);
 
 // Kernel launchers (asynchronous on `stream`; return the launch error).
 hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule& sc,

@@ -251,8 +251,13 @@ __device__ __forceinline__ ChunkCtl chunk_ctl(const uint64_t* records, uint32_t 
     return c;
 }
 
+// One pixel per thread: five workgroups per CU (at most 96 VGPRs, 32 KB of
+// LDS each), so that a 640x480 sensor's 1200 tiles are all resident at once.
+template <int PPT>
+constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : 1; }
+
 template <int PPT, int BK>
-__global__ __launch_bounds__(kBlock) void k_integrate(
+__global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     const uint64_t* __restrict__ records, const uint32_t* __restrict__ table,
     const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t, int K, StateDev st,
     MethodParams mp, FrameOut fo, DiagDev* diag)

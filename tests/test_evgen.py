@@ -1,0 +1,116 @@
+"""The seeded workload generator: determinism, stream invariants and sizes.
+
+The generator holds none of the integration method; these tests pin that
+its streams have the structure the parity tests and the benchmark rely on:
+time-sorted int64 microseconds, in-range pixels, polarity +1/-1, the
+event counts of the three workloads (1M, 20M, 150M, each within 5%), and
+the same output for the same seed whatever the thread count.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import evgen
+
+
+def _short(name, duration_us, **kw):
+    spec = evgen.PRESETS[name]
+    return dataclasses.replace(spec, duration_us=duration_us, **kw)
+
+
+def _check_stream(s):
+    assert s.x.dtype == np.uint16 and s.y.dtype == np.uint16
+    assert s.t.dtype == np.int64 and s.p.dtype == np.int8
+    assert s.x.size == s.y.size == s.t.size == s.p.size
+    assert np.all(s.x < s.width) and np.all(s.y < s.height)
+    assert np.all(np.diff(s.t) >= 0)
+    assert s.t.size == 0 or (s.t[0] >= 0 and s.t[-1] < s.duration_us)
+    assert set(np.unique(s.p).tolist()) <= {-1, 1}
+
+
+def test_c1_invariants_and_count():
+    s = evgen.preset("c1")
+    _check_stream(s)
+    # 0.95M scene events plus 5% noise: about 1M
+    assert abs(s.n - 1.0e6) <= 0.05 * 1.0e6, s.n
+    # both polarities occur in comparable numbers (a drifting grating)
+    pos = int((s.p > 0).sum())
+    assert 0.4 < pos / s.n < 0.6
+
+
+def test_same_seed_same_stream_any_thread_count():
+    spec = _short("c1", 200_000)
+    a = evgen.generate(spec, threads=1)
+    b = evgen.generate(spec, threads=5)
+    for f in ("x", "y", "t", "p"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    c = evgen.generate(dataclasses.replace(spec, seed=spec.seed + 1), threads=3)
+    assert c.n != a.n or not np.array_equal(c.t, a.t)
+
+
+def test_c2_count_and_noise_share():
+    s = evgen.preset("c2")
+    _check_stream(s)
+    # 18M texture events plus 10% noise: about 20M
+    assert abs(s.n - 19.8e6) <= 0.05 * 19.8e6, s.n
+    # events keep coming over the whole 10 s (a random walk, never at rest
+    # for long): every second holds a few percent of the stream at least
+    per_s = np.bincount((s.t // 1_000_000).astype(np.int64), minlength=10)
+    assert per_s.size == 10 and per_s.min() > 0.02 * s.n
+
+
+def test_c3_rate_on_a_slice():
+    # 150M events in 5 s at a constant rotation rate: 6M per 0.2 s once the
+    # first edge passages (which start every pixel's reference level) are over
+    s = evgen.generate(_short("c3", 300_000))
+    _check_stream(s)
+    m = int(((s.t >= 100_000) & (s.t < 300_000)).sum())
+    assert abs(m - 6.0e6) <= 0.05 * 6.0e6, m
+
+
+def test_retune_reproduces_stored_parameter():
+    # The stored grating amplitude is what bisection on the count finds.  The
+    # count of a noiseless grating is a step function of the amplitude (whole
+    # threshold crossings per pixel), so the bisection ends on a step; the
+    # stored, rounded value is the one whose count test_c1 checks.
+    spec = _short("c1", 1_000_000, tune=True)
+    s = evgen.generate(spec)
+    assert abs(s.tuned - evgen.PRESETS["c1"].amplitude) <= 0.01 * evgen.PRESETS["c1"].amplitude
+
+
+def test_frame_times():
+    s = evgen.generate(_short("c1", 1_000_000))
+    tf = s.frame_times(100)
+    assert tf.dtype == np.int64 and tf.size == 100
+    assert tf[0] == 10_000 and tf[-1] == 1_000_000 and np.all(np.diff(tf) == 10_000)
+    assert s.frame_times(1000).size == 1000
+
+
+def test_random_stream_options():
+    s = evgen.random_stream(7, 50, 40, 20000, 1_000_000, burst_frac=0.3, oob_frac=0.1)
+    assert np.all(np.diff(s.t) >= 0)
+    oob = (s.x >= 50) | (s.y >= 40)
+    assert 0.07 < oob.mean() < 0.13
+    same_t = np.mean(np.diff(s.t) == 0)
+    assert same_t > 0.15  # copies of a predecessor's time (natural ties are rare)
+    u = evgen.random_stream(7, 50, 40, 2000, 1_000_000, sorted_=False, pol01=True)
+    assert np.any(np.diff(u.t) < 0)
+    assert set(np.unique(u.p).tolist()) <= {0, 1}
+    again = evgen.random_stream(7, 50, 40, 20000, 1_000_000, burst_frac=0.3, oob_frac=0.1)
+    assert np.array_equal(s.t, again.t) and np.array_equal(s.x, again.x)
+
+
+def test_hot_pixel_stream():
+    s = evgen.hot_pixel_stream(3, 32, 16, 1000, 100_000, hot=[(5, 7), (31, 15)], hot_period_us=10)
+    assert np.all(np.diff(s.t) >= 0)
+    for hx, hy in [(5, 7), (31, 15)]:
+        m = (s.x == hx) & (s.y == hy) & (s.p == 1)
+        assert m.sum() >= 100_000 // 10
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_preset_metadata(name):
+    spec = evgen.PRESETS[name]
+    assert spec.width * spec.height in (346 * 260, 640 * 480, 1280 * 720)
+    assert spec.seed == {"c1": 1, "c2": 2, "c3": 3}[name]

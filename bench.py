@@ -42,6 +42,28 @@ def algorithmic_bytes(n: int, npix: int, nf: int, u8: bool) -> int:
     return 13 * n + 40 * npix + (4 + (1 if u8 else 0)) * nf * npix
 
 
+def measured_traffic(workload: str, fps: float):
+    """HBM bytes per launch of the integration kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    reading of a plain copy of known size), or None when no summary exists for
+    this workload or the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_integrate_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if float(rec.get("fps", 100.0)) != fps:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+        return None
+    return int(rec["read_bytes"]) + int(rec["write_bytes"])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,7 +166,7 @@ def main() -> int:
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(alg / (integ_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": None if args.u8 else measured_traffic(args.workload, args.fps),
         "algorithmic_bytes": alg,
         "avg_launch_ms": round(integ_avg_ms, 4),
     }

@@ -10,10 +10,10 @@
  *
  * What it computes, in the paper's order (Sec. III, Alg. 1 and Alg. 2):
  *   per event e_i = (x_i, y_i, p_i, t_i), in array order:
- *     S(x,y) <- S(x,y) + p_i * C                       (Alg. 2, "update accumulation")
- *     dt     <- t_i - T(x,y)                           (Alg. 2, "time difference")
- *     S(x,y) <- S(x,y) * d(dt),  d from Eq. (4)        (Alg. 2, "decay")
- *     T(x,y) <- t_i                                    (Alg. 2, "update last decay time")
+ *     S(x,y) <- S(x,y) + p_i * C                       (Alg. 2: accumulate the event)
+ *     dt     <- t_i - T(x,y)                           (Alg. 2: time since the last event)
+ *     S(x,y) <- S(x,y) * d(dt),  d from Eq. (4)        (Alg. 2: decay step)
+ *     T(x,y) <- t_i                                    (Alg. 2: new last-event time)
  *     S(x,y) <- min(max(S, S_min), S_max)              (Eq. (13), applied per event as in Alg. 2)
  *   frame:  B = (S - S_min) / (S_max - S_min)           (Eq. (14), normalised to [0,1];
  *                                                        the 8-bit code is 255 times this)

@@ -26,6 +26,7 @@ struct esi_state {
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     int bucket_slots = 1024;  // bucketing workgroups resident at once
+    bool state_in_range = true;  // every S in [s_min, s_max] (false after importing one outside)
     bool poisoned = false;
     uint64_t calls = 0;
     // profiling: HIP events around the two phases of recorded calls
@@ -65,6 +66,11 @@ MethodParams method_params(const esi_params& p)
     mp.s_max = p.s_max;
     mp.inv_range = 1.0 / (p.s_max - p.s_min);
     mp.f_off = -p.s_min * mp.inv_range;
+    mp.sv_min = p.s_min * mp.inv_range;
+    mp.sv_max = p.s_max * mp.inv_range;
+    // a state in [s_min, s_max] decays towards 0, so it stays in range when
+    // s_min <= 0 <= s_max
+    mp.need_clamp = (p.s_min > 0.0 || p.s_max < 0.0) ? 1 : 0;
     mp.decay_then_add = (p.flags & ESI_DECAY_THEN_ADD) ? 1 : 0;
     mp.lazy = (p.flags & ESI_SNAPSHOT_LAZY) ? 1 : 0;
     return mp;
@@ -260,6 +266,7 @@ esi_status esi_reset(esi_state* st, hipStream_t stream)
     if (launch_reset(st->dev, st->params.t0_us, st->diag, stream) != hipSuccess)
         return hip_fail(st);
     st->poisoned = false;
+    st->state_in_range = true;
     st->calls = 0;
     return ESI_OK;
 }
@@ -282,7 +289,9 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
         return ESI_ERR_POISONED;
     DeviceGuard g(st->device);
     const int64_t n = (int64_t)ev->n;
-    const MethodParams mp = method_params(st->params);
+    MethodParams mp = method_params(st->params);
+    if (!st->state_in_range)
+        mp.need_clamp = 1;
     const Schedule sc = make_schedule(st->npix, n, st->bucket_slots);
     EventsDev evd{ev->x, ev->y, ev->t, ev->p, n};
     CallScratch cs{};
@@ -429,6 +438,17 @@ esi_status esi_import_state(esi_state* st, const void* host_buf, size_t bytes)
         hipMemcpy(st->dev.P, p + 20 * n, 4 * n, hipMemcpyHostToDevice) ||
         hipMemcpy(st->diag, &d, sizeof(d), hipMemcpyHostToDevice))
         return hip_fail(st);
+    // frames may skip the clamp of a decayed state only while every S is in
+    // [s_min, s_max] (S = hi + lo, as the kernels read it)
+    bool in_range = true;
+    for (size_t q = 0; q < n && in_range; ++q) {
+        float hi, lo;
+        std::memcpy(&hi, p + 4 * q, 4);
+        std::memcpy(&lo, p + 4 * n + 4 * q, 4);
+        const double s = (double)hi + (double)lo;
+        in_range = s >= st->params.s_min && s <= st->params.s_max;
+    }
+    st->state_in_range = in_range;
     st->poisoned = false;
     return ESI_OK;
 }

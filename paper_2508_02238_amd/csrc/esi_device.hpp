@@ -21,8 +21,10 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 struct MethodParams {
     double C, k, b, s_min, s_max, inv_range;  // inv_range = 1 / (s_max - s_min)
     double f_off;                             // -s_min * inv_range
+    double sv_min, sv_max;                    // s_min * inv_range, s_max * inv_range
     int decay_then_add;
     int lazy;
+    int need_clamp;  // a decayed state can leave [s_min, s_max]
 };
 
 // How d = max(1 - k dt, 0)^b is evaluated: b = 1 and b = 2 exactly by

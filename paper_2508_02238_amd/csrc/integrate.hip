@@ -56,9 +56,9 @@ template <int PPT>
 struct TileCfg {
     static constexpr int TILE = kBlock * PPT;
     // records per chunk: LDS holds them three times over (records, states,
-    // frame indices) next to the (pixel, wave) counters of the tile; sized so
-    // that five workgroups of one pixel per thread share a CU
-    static constexpr int CHUNK = PPT == 1 ? 1536 : (PPT == 2 ? 1280 : 1024);
+    // frame indices) next to the (pixel, wave) counters of the tile; at one
+    // pixel per thread five workgroups share a CU
+    static constexpr int CHUNK = PPT == 2 ? 1280 : 1024;
     static constexpr int PER_WAVE = CHUNK / kWavesPerBlock;  // records per wave per chunk
     static constexpr int STEPS = PER_WAVE / kWave;           // records per lane per chunk
 };
@@ -110,81 +110,101 @@ struct Pixels {
     int64_t T[PPT];
     uint32_t N[PPT];
     int32_t P[PPT];
-    // the state the frames see: Sf and Af = 1 + k (Tf - t_b)
-    double Sf[PPT], Af[PPT];
-    // change list of the segment: entries [.., cend) of chg_*, nx = next to load
-    uint32_t nx[PPT], cend[PPT];
-    int jn[PPT], jn2[PPT];      // frame indices of the next two changes
-    double Sn[PPT], An[PPT];    // the next change
-    double Sn2[PPT], An2[PPT];  // the one after
+    // the state the frames see: Sv = S / (s_max - s_min) and Av = 1 + k (T - t_b)
+    double Sv[PPT], Av[PPT];
+    // change list of the segment: next entry to load
+    uint32_t nx[PPT];
+    int jn[PPT];              // segment frame of the next change (>= kFrameGroup: none)
+    double Sn[PPT], An[PPT];  // its state
 };
 
+// Load the next change of pixel slot i.  Pixel l's frame indices sit at
+// chg_j[entry + l] and are followed by a 0xFFFF sentinel, so no test of the
+// list's end is needed; states are read at a clamped index.
 template <int PPT, int CH>
-__device__ __forceinline__ void load_change(Pixels<PPT>& px, int i, const double* chg_S,
-                                            const double* chg_A, const uint16_t* chg_j, int& jv,
-                                            double& Sv, double& Av)
+__device__ __forceinline__ void next_change(Pixels<PPT>& px, int i, int l, const double* chg_S,
+                                            const double* chg_A, const uint16_t* chg_j)
 {
     const uint32_t e = min(px.nx[i], (uint32_t)(CH - 1));
-    Sv = chg_S[e];
-    Av = chg_A[e];
-    jv = (px.nx[i] < px.cend[i]) ? (int)chg_j[e] : kNever;
+    px.Sn[i] = chg_S[e];
+    px.An[i] = chg_A[e];
+    px.jn[i] = chg_j[px.nx[i] + l];
     ++px.nx[i];
 }
 
 // One frame (index jj of the segment) of Eq. (14): take the pixel's next
-// change if it belongs to this frame, then v = clamp(Sf u^b) with
-// u = clamp(Af - kt, 0, 1) (v = Sf for the lazy snapshot) and
-// F = (v - s_min) / (s_max - s_min).  OUT: 1 FP32 frames, 2 8-bit codes, 3 both.
-template <int PPT, int BK, bool LAZY, int OUT, int CH>
+// change if it belongs to this frame, then
+//   F = clamp(Sv u^b) + f_off,  u = clamp(Av - kt, 0, 1)    (decayed snapshot)
+//   F = Sv + f_off                                        (lazy snapshot)
+// with Sv = S / (s_max - s_min) and f_off = -s_min / (s_max - s_min), i.e.
+// F = (v - s_min) / (s_max - s_min).  CLAMP: the clamp of Eq. (13) on the
+// decayed value, a no-op when s_min <= 0 <= s_max and the state is in range
+// (then Sv u^b lies between 0 and Sv).  OUT: 1 FP32 frames, 2 8-bit codes,
+// 3 both.  FULL: every pixel slot of the tile is on the sensor.
+template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT, bool FULL, int CH>
 __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& px, int jj, double kt,
                                            const double* chg_S, const double* chg_A,
                                            const uint16_t* chg_j, float* frow, uint8_t* urow,
-                                           const uint32_t (&off)[PPT], const bool (&in)[PPT])
+                                           const bool (&in)[PPT])
 {
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
+        const int l = (int)threadIdx.x + i * kBlock;
         if (px.jn[i] == jj) {
-            px.Sf[i] = px.Sn[i];
-            px.Af[i] = px.An[i];
-            px.jn[i] = px.jn2[i];
-            px.Sn[i] = px.Sn2[i];
-            px.An[i] = px.An2[i];
-            load_change<PPT, CH>(px, i, chg_S, chg_A, chg_j, px.jn2[i], px.Sn2[i], px.An2[i]);
+            px.Sv[i] = px.Sn[i];
+            px.Av[i] = px.An[i];
+            next_change<PPT, CH>(px, i, l, chg_S, chg_A, chg_j);
         }
-        double v = px.Sf[i];
-        if (!LAZY) {
-            const double u = fmin(fmax(px.Af[i] - kt, 0.0), 1.0);
-            v = clamp_s(mp, v * power_b<BK>(u, mp.b));
+        double F;
+        if (LAZY) {
+            F = px.Sv[i] + mp.f_off;
+        } else {
+            const double u = fmin(fmax(px.Av[i] - kt, 0.0), 1.0);
+            if (BK == kDecayB2 && !CLAMP) {
+                F = __fma_rn(px.Sv[i] * u, u, mp.f_off);
+            } else if (BK == kDecayB1 && !CLAMP) {
+                F = __fma_rn(px.Sv[i], u, mp.f_off);
+            } else {
+                double w = px.Sv[i] * power_b<BK>(u, mp.b);
+                if (CLAMP)
+                    w = fmin(fmax(w, mp.sv_min), mp.sv_max);
+                F = w + mp.f_off;
+            }
         }
-        const float F = (float)__fma_rn(v, mp.inv_range, mp.f_off);
-        if (in[i]) {
+        const float Ff = (float)F;
+        if (FULL || in[i]) {
             if (OUT & 1)
-                __builtin_nontemporal_store(F, frow + off[i]);
+                __builtin_nontemporal_store(Ff, frow + l);
             if (OUT & 2)
-                urow[off[i]] = frame_code(F);
+                urow[l] = frame_code(Ff);
         }
     }
 }
 
 // Phase B over the nfw frames of one segment; frow / urow point at the
-// tile's piece of the segment's first frame; ktl[jj] = k (t_f - t_b).
-template <int PPT, int BK, bool LAZY, int OUT, int CH>
+// tile's piece of the segment's first frame; ktl[jj] = k (t_f - t_b), read
+// two frames at a time one pair ahead.
+template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT, bool FULL, int CH>
 __device__ __forceinline__ void walk_segment(const MethodParams& mp, Pixels<PPT>& px, int nfw,
                                              const double* ktl, const double* chg_S,
                                              const double* chg_A, const uint16_t* chg_j,
                                              float* frow, uint8_t* urow, int64_t npix,
-                                             const uint32_t (&off)[PPT], const bool (&in)[PPT])
+                                             const bool (&in)[PPT])
 {
+    const double2* kt2 = reinterpret_cast<const double2*>(ktl);
+    double2 kk = kt2[0];
     for (int jj = 0; jj < nfw; jj += 2) {
-        const double2 kk = *reinterpret_cast<const double2*>(ktl + jj);
-        frame_step<PPT, BK, LAZY, OUT, CH>(mp, px, jj, kk.x, chg_S, chg_A, chg_j, frow, urow, off, in);
+        const double2 cur = kk;
+        kk = kt2[min(jj / 2 + 1, kFrameGroup / 2 - 1)];
+        frame_step<PPT, BK, LAZY, CLAMP, OUT, FULL, CH>(mp, px, jj, cur.x, chg_S, chg_A, chg_j,
+                                                        frow, urow, in);
         if (OUT & 1)
             frow += npix;
         if (OUT & 2)
             urow += npix;
         if (jj + 1 < nfw) {
-            frame_step<PPT, BK, LAZY, OUT, CH>(mp, px, jj + 1, kk.y, chg_S, chg_A, chg_j, frow, urow,
-                                               off, in);
+            frame_step<PPT, BK, LAZY, CLAMP, OUT, FULL, CH>(mp, px, jj + 1, cur.y, chg_S, chg_A,
+                                                            chg_j, frow, urow, in);
             if (OUT & 1)
                 frow += npix;
             if (OUT & 2)
@@ -193,11 +213,12 @@ __device__ __forceinline__ void walk_segment(const MethodParams& mp, Pixels<PPT>
     }
 }
 
-// Output mode of a call: 0-2 decayed snapshots (FP32, 8-bit, both), 3-5 lazy.
-__device__ __forceinline__ int walk_mode(const MethodParams& mp, const FrameOut& fo)
+// Output mode of a call: 0-2 decayed snapshots (FP32, 8-bit, both), 3-5 the
+// same with the clamp, 6-8 lazy; +9 for a tile with pixel slots off the sensor.
+__device__ __forceinline__ int walk_mode(const MethodParams& mp, const FrameOut& fo, bool full)
 {
     const int out = (fo.frames && fo.frames_u8) ? 2 : (fo.frames ? 0 : 1);
-    return (mp.lazy ? 3 : 0) + out;
+    return (mp.lazy ? 6 : (mp.need_clamp ? 3 : 0)) + out + (full ? 0 : 9);
 }
 
 template <int PPT, int BK, int CH>
@@ -205,28 +226,32 @@ __device__ __forceinline__ void walk_dispatch(int mode, const MethodParams& mp, 
                                               int nfw, const double* ktl, const double* chg_S,
                                               const double* chg_A, const uint16_t* chg_j,
                                               float* frow, uint8_t* urow, int64_t npix,
-                                              const uint32_t (&off)[PPT], const bool (&in)[PPT])
+                                              const bool (&in)[PPT])
 {
+#define ESI_WALK(L, C, O, F)                                                                   \
+    walk_segment<PPT, BK, L, C, O, F, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, \
+                                          npix, in)
     switch (mode) {
-    case 0:
-        walk_segment<PPT, BK, false, 1, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
-        break;
-    case 1:
-        walk_segment<PPT, BK, false, 2, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
-        break;
-    case 2:
-        walk_segment<PPT, BK, false, 3, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
-        break;
-    case 3:
-        walk_segment<PPT, BK, true, 1, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
-        break;
-    case 4:
-        walk_segment<PPT, BK, true, 2, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
-        break;
-    default:
-        walk_segment<PPT, BK, true, 3, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, npix, off, in);
-        break;
+    case 0: ESI_WALK(false, false, 1, true); break;
+    case 1: ESI_WALK(false, false, 2, true); break;
+    case 2: ESI_WALK(false, false, 3, true); break;
+    case 3: ESI_WALK(false, true, 1, true); break;
+    case 4: ESI_WALK(false, true, 2, true); break;
+    case 5: ESI_WALK(false, true, 3, true); break;
+    case 6: ESI_WALK(true, false, 1, true); break;
+    case 7: ESI_WALK(true, false, 2, true); break;
+    case 8: ESI_WALK(true, false, 3, true); break;
+    case 9: ESI_WALK(false, false, 1, false); break;
+    case 10: ESI_WALK(false, false, 2, false); break;
+    case 11: ESI_WALK(false, false, 3, false); break;
+    case 12: ESI_WALK(false, true, 1, false); break;
+    case 13: ESI_WALK(false, true, 2, false); break;
+    case 14: ESI_WALK(false, true, 3, false); break;
+    case 15: ESI_WALK(true, false, 1, false); break;
+    case 16: ESI_WALK(true, false, 2, false); break;
+    default: ESI_WALK(true, false, 3, false); break;
     }
+#undef ESI_WALK
 }
 
 // Scalars that place one chunk: its record window [cs, cs + avail), the
@@ -272,7 +297,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     static_assert(CHUNK < 65536, "16-bit counters");
     __shared__ uint64_t sorted[CHUNK];    // records sorted by pixel (frame index over the pixel field)
     __shared__ double chg_S[CHUNK];       // change lists: S after the change
-    __shared__ uint16_t chg_j[CHUNK];     // change lists: frame index in the segment
+    __shared__ uint16_t chg_j[CHUNK + TILE];  // change lists: frame index in the segment
     __shared__ uint16_t cnt[kWavesPerBlock][TILE];
     __shared__ int64_t tfl[kFrameGroup];  // frame times of the segment
     __shared__ __align__(16) double ktl[kFrameGroup];  // k (t_f - t_b) of the segment's frames
@@ -287,16 +312,14 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     const int64_t npix = st.npix;
     const int kbits = key_bits_for((uint32_t)TILE);
     const int nf = fo.nf;
-    const int mode = walk_mode(mp, fo);
+    const int mode = walk_mode(mp, fo, (int64_t)(tile + 1) * TILE <= npix);
 
     Pixels<PPT> px;
-    uint32_t off[PPT];
     bool in[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int64_t q = q0 + (int64_t)i * kBlock;
         in[i] = q < npix;
-        off[i] = (uint32_t)(tid + i * kBlock);
         px.S[i] = in[i] ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
         px.T[i] = in[i] ? st.T[q] : 0;
         px.N[i] = in[i] ? st.N[q] : 0u;
@@ -363,16 +386,16 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                 rr_next[s] = records[ce + min((uint32_t)(wave * PER_WAVE + s * kWave + lane), avail1 - 1u)];
         }
 
-        // the segment's frame times and decay bases; the visible state
-        // before this chunk's events
+        // the segment's frame times; the visible state before this chunk's
+        // events
         if (tid < kFrameGroup) {
             tfl[tid] = tfv;
             ktl[tid] = mp.k * (double)(tfv - tb);
         }
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            px.Sf[i] = px.S[i];
-            px.Af[i] = __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
+            px.Sv[i] = px.S[i] * mp.inv_range;
+            px.Av[i] = __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
         }
         uint32_t rank[STEPS];
         if (cn > 0) {
@@ -457,41 +480,45 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
 
             // 3. phase A: each pixel's events of the chunk in array order; the
             // change list keeps, per segment frame jc that first includes
-            // some event, the state after the last such event.  Entries go
-            // over the pixel's own slots of `sorted`/chg_*, behind the read
-            // position.  Events after the segment (jc == nfw) make no entry.
+            // some event, the state after the last such event, written once
+            // the next event belongs to a later frame (or the run ends).
+            // Entries go over the pixel's own slots of `sorted`/chg_*, behind
+            // the read position.  Events after the segment (jc == nfw) make
+            // no entry.
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 const int l = tid + i * kBlock;
                 const uint32_t end = min((l + 1 < TILE) ? (uint32_t)cnt[0][l + 1] : cn, cn);
                 const uint32_t beg = min((uint32_t)cnt[0][l], end);
                 uint32_t w = beg;
-                int jc_prev = -1;
+                int jc_prev = nfw;  // frame of the events applied so far (nfw: none)
                 for (uint32_t e = beg; e < end; ++e) {
                     const uint64_t r = sorted[e];
-                    const int64_t t = t_ref + record_dt(r);
-                    apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t, record_pos(r));
                     const int jc = (int)record_lpx(r);
-                    if (jc < nfw) {
-                        if (jc != jc_prev && jc_prev >= 0)
-                            ++w;  // a new entry; the previous one is final
-                        chg_S[w] = px.S[i];
-                        chg_A[w] = __fma_rn(mp.k, (double)(t - tb), 1.0);
-                        chg_j[w] = (uint16_t)jc;
-                        jc_prev = jc;
+                    if (jc != jc_prev && jc_prev < nfw) {
+                        chg_S[w] = px.S[i] * mp.inv_range;
+                        chg_A[w] = __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
+                        chg_j[w + l] = (uint16_t)jc_prev;
+                        ++w;
                     }
+                    jc_prev = jc;
+                    apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t_ref + record_dt(r),
+                                    record_pos(r));
                 }
+                if (jc_prev < nfw) {
+                    chg_S[w] = px.S[i] * mp.inv_range;
+                    chg_A[w] = __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
+                    chg_j[w + l] = (uint16_t)jc_prev;
+                    ++w;
+                }
+                chg_j[w + l] = 0xFFFF;  // end of the list
                 px.nx[i] = beg;
-                px.cend[i] = (jc_prev >= 0) ? w + 1u : beg;
-                load_change<PPT, CHUNK>(px, i, chg_S, chg_A, chg_j, px.jn[i], px.Sn[i], px.An[i]);
-                load_change<PPT, CHUNK>(px, i, chg_S, chg_A, chg_j, px.jn2[i], px.Sn2[i], px.An2[i]);
+                next_change<PPT, CHUNK>(px, i, l, chg_S, chg_A, chg_j);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) {
+            for (int i = 0; i < PPT; ++i)
                 px.jn[i] = kNever;
-                px.jn2[i] = kNever;
-            }
         }
 
         // Wait for the prefetched records and frame times now: this also
@@ -503,7 +530,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             const size_t base = (size_t)j * (size_t)npix + (size_t)tile * TILE;
             walk_dispatch<PPT, BK, CHUNK>(mode, mp, px, nfw, ktl, chg_S, chg_A, chg_j,
                                           fo.frames ? fo.frames + base : nullptr,
-                                          fo.frames_u8 ? fo.frames_u8 + base : nullptr, npix, off, in);
+                                          fo.frames_u8 ? fo.frames_u8 + base : nullptr, npix, in);
         }
         j = j_end;
         cs = ce;

@@ -174,7 +174,7 @@ __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& 
         const float Ff = (float)F;
         if (FULL || in[i]) {
             if (OUT & 1)
-                __builtin_nontemporal_store(Ff, frow + l);
+                frow[l] = Ff;
             if (OUT & 2)
                 urow[l] = frame_code(Ff);
         }
@@ -259,6 +259,7 @@ __device__ __forceinline__ void walk_dispatch(int mode, const MethodParams& mp, 
 // frame times that bound its segment.
 struct ChunkCtl {
     uint32_t avail;
+    int64_t t_first;          // time of the window's first record (0 if none)
     int64_t t_last, t_after;  // t_after = INT64_MAX when the window ends the tile
     int64_t tb, tf_hi;        // frame j and frame min(j + kFrameGroup, nf) - 1
 };
@@ -269,6 +270,7 @@ __device__ __forceinline__ ChunkCtl chunk_ctl(const uint64_t* records, uint32_t 
 {
     ChunkCtl c;
     c.avail = min((uint32_t)CHUNK, re - cs);
+    c.t_first = c.avail ? t_ref + record_dt(load_const(records, cs)) : 0;
     c.t_last = c.avail ? t_ref + record_dt(load_const(records, cs + c.avail - 1)) : 0;
     c.t_after = (cs + c.avail < re) ? t_ref + record_dt(load_const(records, cs + c.avail)) : INT64_MAX;
     c.tb = (j < fo.nf) ? load_const(fo.t_frames, j) : 0;
@@ -296,7 +298,8 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     static_assert(PER_WAVE % kWave == 0, "chunk size");
     static_assert(CHUNK < 65536, "16-bit counters");
     __shared__ uint64_t sorted[CHUNK];    // records sorted by pixel (frame index over the pixel field)
-    __shared__ double chg_S[CHUNK];       // change lists: S after the change
+    __shared__ double ktvs[CHUNK];        // k (t - t_first) of the sorted records; then
+    double* chg_S = ktvs;                 // change lists: S / (s_max - s_min) after the change
     __shared__ uint16_t chg_j[CHUNK + TILE];  // change lists: frame index in the segment
     __shared__ uint16_t cnt[kWavesPerBlock][TILE];
     __shared__ int64_t tfl[kFrameGroup];  // frame times of the segment
@@ -463,26 +466,34 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             }
             __syncthreads();
             // 2d. scatter into pixel order, the frame index over the pixel
-            // field (every index is checked, so that a broken invariant can
-            // only flag an error, never leave the chunk)
+            // field, and each record's k (t - t_first) (every index is
+            // checked, so that a broken invariant can only flag an error,
+            // never leave the chunk)
+            const int64_t dt_first = c.t_first - t_ref;
 #pragma unroll
             for (int s = 0; s < STEPS; ++s) {
                 const uint32_t c_ = (uint32_t)(wave * PER_WAVE + s * kWave + lane);
                 if (c_ < cn) {
                     const uint32_t at = (uint32_t)cnt[wave][record_lpx(rr[s]) & (TILE - 1)] + (rank[s] & 0xFFFFu);
-                    if (at < cn)
+                    if (at < cn) {
                         sorted[at] = (rr[s] & ~kLpxMask) | ((uint64_t)(rank[s] >> 16) << 48);
-                    else
+                        ktvs[at] = mp.k * (double)(record_dt(rr[s]) - dt_first);
+                    } else {
                         bad = true;
+                    }
                 }
             }
             __syncthreads();
 
-            // 3. phase A: each pixel's events of the chunk in array order; the
-            // change list keeps, per segment frame jc that first includes
+            // 3. phase A: each pixel's events of the chunk in array order
+            // (Alg. 2).  With A = 1 + k (T - t_first) per pixel and
+            // kt = k (t - t_first) per event, the base of Eq. (4) is
+            // u = clamp(A - kt, 0, 1) = max(1 - k max(t - T, 0), 0), and after
+            // the event A = 1 + kt.  N, P and T are settled once per run.
+            // The change list keeps, per segment frame jc that first includes
             // some event, the state after the last such event, written once
             // the next event belongs to a later frame (or the run ends).
-            // Entries go over the pixel's own slots of `sorted`/chg_*, behind
+            // Entries go over the pixel's own slots of `sorted`/`ktvs`, behind
             // the read position.  Events after the segment (jc == nfw) make
             // no entry.
 #pragma unroll
@@ -490,27 +501,42 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                 const int l = tid + i * kBlock;
                 const uint32_t end = min((l + 1 < TILE) ? (uint32_t)cnt[0][l + 1] : cn, cn);
                 const uint32_t beg = min((uint32_t)cnt[0][l], end);
-                uint32_t w = beg;
+                double S = px.S[i];
+                double A = __fma_rn(mp.k, (double)(px.T[i] - c.t_first), 1.0);
+                uint64_t r_prev = 0;
+                uint32_t w = beg, npos = 0;
                 int jc_prev = nfw;  // frame of the events applied so far (nfw: none)
                 for (uint32_t e = beg; e < end; ++e) {
                     const uint64_t r = sorted[e];
+                    const double kt = ktvs[e];
                     const int jc = (int)record_lpx(r);
                     if (jc != jc_prev && jc_prev < nfw) {
-                        chg_S[w] = px.S[i] * mp.inv_range;
-                        chg_A[w] = __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
+                        chg_S[w] = S * mp.inv_range;
+                        chg_A[w] = __fma_rn(mp.k, (double)(t_ref + record_dt(r_prev) - tb), 1.0);
                         chg_j[w + l] = (uint16_t)jc_prev;
                         ++w;
                     }
                     jc_prev = jc;
-                    apply_event<BK>(mp, px.S[i], px.T[i], px.N[i], px.P[i], t_ref + record_dt(r),
-                                    record_pos(r));
+                    const double u = fmin(fmax(A - kt, 0.0), 1.0);
+                    const double d = power_b<BK>(u, mp.b);
+                    const int pos = record_pos(r);
+                    const double s = pos ? mp.C : -mp.C;
+                    S = clamp_s(mp, mp.decay_then_add ? __fma_rn(S, d, s) : (S + s) * d);
+                    A = 1.0 + kt;
+                    npos += (uint32_t)pos;
+                    r_prev = r;
                 }
                 if (jc_prev < nfw) {
-                    chg_S[w] = px.S[i] * mp.inv_range;
-                    chg_A[w] = __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
+                    chg_S[w] = S * mp.inv_range;
+                    chg_A[w] = __fma_rn(mp.k, (double)(t_ref + record_dt(r_prev) - tb), 1.0);
                     chg_j[w + l] = (uint16_t)jc_prev;
                     ++w;
                 }
+                px.S[i] = S;
+                if (end > beg)
+                    px.T[i] = t_ref + record_dt(r_prev);
+                px.N[i] += end - beg;
+                px.P[i] += 2 * (int32_t)npos - (int32_t)(end - beg);
                 chg_j[w + l] = 0xFFFF;  // end of the list
                 px.nx[i] = beg;
                 next_change<PPT, CHUNK>(px, i, l, chg_S, chg_A, chg_j);

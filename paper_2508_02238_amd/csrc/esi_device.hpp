@@ -170,6 +170,40 @@ __device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, int 
     return base + r;
 }
 
+// The same stable rank through LDS, in rounds: in each round every valid lane
+// not ranked yet posts a priority for its key with an atomic max, and the
+// lowest lane of each key (the highest priority) takes counter[key] and
+// advances it; distinct keys in a round make those updates independent.
+// Priorities carry a round sequence number (`seq`, kept by the caller and
+// increasing across calls) in the high bits, so `slot` never needs clearing:
+// a later round's value always exceeds an earlier one.  A step costs one
+// round per lane of the most frequent key (usually one or two), against one
+// ballot per key bit in wave_stable_rank.  slot: one word per key, zeroed
+// once before the first call.
+template <typename CounterT>
+__device__ __forceinline__ uint32_t wave_stable_rank_lds(bool ok, uint32_t key, CounterT* counter,
+                                                         uint32_t* slot, uint32_t& seq)
+{
+    const uint32_t lane = __lane_id();
+    uint32_t rank = 0;
+    bool mine = ok;
+    while (__ballot(mine)) {
+        ++seq;
+        const uint32_t prio = (seq << 6) | (uint32_t)(kWave - 1 - lane);
+        if (mine)
+            atomicMax(&slot[key], prio);
+        wave_sync();
+        const bool win = mine && slot[key] == prio;
+        if (win) {
+            rank = (uint32_t)counter[key];
+            counter[key] = (CounterT)(rank + 1u);
+        }
+        wave_sync();
+        mine = mine && !win;
+    }
+    return rank;
+}
+
 // Bits needed for keys in [0, n).
 __host__ __device__ inline int key_bits_for(uint32_t n)
 {

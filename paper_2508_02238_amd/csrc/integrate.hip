@@ -153,6 +153,9 @@ __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& 
         if (px.jn[i] == jj) {
             px.Sv[i] = px.Sn[i];
             px.Av[i] = px.An[i];
+            // keep the loads below the moves, so that they can land in the
+            // registers of Sn / An themselves (no copies on the other path)
+            __builtin_amdgcn_sched_barrier(0);
             next_change<PPT, CH>(px, i, l, chg_S, chg_A, chg_j);
         }
         double F;
@@ -302,6 +305,10 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     double* chg_S = ktvs;                 // change lists: S / (s_max - s_min) after the change
     __shared__ uint16_t chg_j[CHUNK + TILE];  // change lists: frame index in the segment
     __shared__ uint16_t cnt[kWavesPerBlock][TILE];
+    // rank priorities per (wave, pixel) for the LDS stable rank (one and two
+    // pixels per thread; larger tiles use the ballot rank)
+    constexpr bool kLdsRank = PPT <= 2;
+    __shared__ uint32_t rslot[kWavesPerBlock][kLdsRank ? TILE : 1];
     __shared__ int64_t tfl[kFrameGroup];  // frame times of the segment
     __shared__ __align__(16) double ktl[kFrameGroup];  // k (t_f - t_b) of the segment's frames
     __shared__ uint32_t scan_w[kWavesPerBlock];
@@ -341,6 +348,11 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     int j = 0;  // first frame of the segment (uniform)
     uint32_t cs = rs;
     bool bad = false;
+    uint32_t rseq = 0;  // rank round sequence number of this wave
+    if (kLdsRank) {
+        for (int k = lane; k < TILE; k += kWave)
+            rslot[wave][k] = 0;
+    }
     ChunkCtl c = chunk_ctl<CHUNK>(records, cs, re, t_ref, fo, j);
 
     // records of the first chunk and the first frame times; clamped indices,
@@ -409,7 +421,11 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
 #pragma unroll
             for (int s = 0; s < STEPS; ++s) {
                 const uint32_t c_ = (uint32_t)(wave * PER_WAVE + s * kWave + lane);
-                rank[s] = wave_stable_rank(c_ < cn, record_lpx(rr[s]) & (TILE - 1), kbits, cnt[wave]);
+                const uint32_t key = record_lpx(rr[s]) & (TILE - 1);
+                if (kLdsRank)
+                    rank[s] = wave_stable_rank_lds(c_ < cn, key, cnt[wave], rslot[wave], rseq);
+                else
+                    rank[s] = wave_stable_rank(c_ < cn, key, kbits, cnt[wave]);
             }
         }
         __syncthreads();

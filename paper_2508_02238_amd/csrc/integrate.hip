@@ -47,7 +47,8 @@ namespace {
 
 // s_waitcnt immediate (gfx9 encoding): vmcnt = 0, expcnt and lgkmcnt not waited.
 constexpr int kWaitVmcnt0 = 0x0F70;
-constexpr int kFrameGroup = 128;                    // frames per segment, at most
+constexpr int kFrameGroup = 96;                     // frames per segment, at most
+constexpr int kSearchTop = 64;                      // largest power of two <= kFrameGroup
 constexpr double kMaxSegmentDecay = 1073741824.0;   // 2^30
 constexpr int kNever = 0x7FFFFFFF;                  // "no further change"
 constexpr uint64_t kLpxMask = (uint64_t)0x7FFF << 48;
@@ -70,36 +71,19 @@ struct FrameOut {
     uint8_t* frames_u8;
 };
 
-// First record index in [lo, hi) whose time is > t (hi if none); records of
-// a tile are in array order, so this is exact for time-sorted input.
-__device__ __forceinline__ uint32_t first_record_after(const uint64_t* rec, uint32_t lo, uint32_t hi,
-                                                       int64_t t_ref, int64_t t)
-{
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (t_ref + record_dt(load_const(rec, mid)) <= t)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // Number of leading entries of tfl[0, n) that are < t (n <= kFrameGroup), in
-// a fixed number of steps; for non-decreasing tfl this is the lower bound.
+// a fixed number of steps (binary lifting: the steps add up to at least
+// kFrameGroup); for non-decreasing tfl this is the lower bound of t.
 __device__ __forceinline__ int frames_before(const int64_t* tfl, int n, int64_t t)
 {
+    static_assert(2 * kSearchTop > kFrameGroup && kSearchTop <= kFrameGroup, "search steps");
     int pos = 0;
 #pragma unroll
-    for (int step = kFrameGroup / 2; step >= 1; step >>= 1) {
+    for (int step = kSearchTop; step >= 1; step >>= 1) {
         const int probe = pos + step;
         const int64_t v = tfl[min(probe, kFrameGroup) - 1];
         pos = (probe <= n && v < t) ? probe : pos;
     }
-    // the last entry (n == kFrameGroup) is covered by the steps above only
-    // up to kFrameGroup - 1
-    if (pos == kFrameGroup - 1 && n == kFrameGroup && tfl[kFrameGroup - 1] < t)
-        pos = kFrameGroup;
     return pos;
 }
 
@@ -312,6 +296,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     __shared__ int64_t tfl[kFrameGroup];  // frame times of the segment
     __shared__ __align__(16) double ktl[kFrameGroup];  // k (t_f - t_b) of the segment's frames
     __shared__ uint32_t scan_w[kWavesPerBlock];
+    __shared__ uint32_t cut_w[kWavesPerBlock];
     double* chg_A = reinterpret_cast<double*>(sorted);  // change lists: A after the change
 
     const int tid = threadIdx.x;
@@ -381,12 +366,29 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             jmax = j + 1;
         const int64_t tf_lim = (jmax < nf) ? (jmax == jmax0 ? c.tf_hi : c.tb) : INT64_MAX;
         uint32_t cn;
-        if (c.avail == 0)
+        if (c.avail == 0) {
             cn = 0;
-        else if (jmax == nf || c.t_last <= tf_lim)
+        } else if (jmax == nf || c.t_last <= tf_lim) {
             cn = c.avail;
-        else
-            cn = first_record_after(records, cs, cs + c.avail, t_ref, tf_lim) - cs;
+        } else {
+            // the segment is full before the window ends: the chunk stops at
+            // the first record later than the segment's last frame (each wave
+            // finds it among the records it holds)
+            uint32_t first = (uint32_t)CHUNK;
+#pragma unroll
+            for (int s = STEPS - 1; s >= 0; --s) {
+                const uint32_t base = (uint32_t)(wave * PER_WAVE + s * kWave);
+                const bool over = base + lane < c.avail && t_ref + record_dt(rr[s]) > tf_lim;
+                const uint64_t m = __ballot(over);
+                if (m)
+                    first = base + (uint32_t)__ffsll((long long)m) - 1u;
+            }
+            if (lane == 0)
+                cut_w[wave] = first;
+            __syncthreads();
+            cn = min(min(cut_w[0], cut_w[1]), min(cut_w[2], cut_w[3]));
+            cn = min(cn, c.avail);
+        }
         const uint32_t ce = cs + cn;
         // frames the chunk completes: all of the segment unless the record
         // after the chunk (t_after) comes before its end

@@ -43,6 +43,8 @@ namespace {
 constexpr int kXcds = 8;
 constexpr int kSegRows = 16;  // table rows (ranges) per segment of the column scan
 constexpr int kSub = 2048;    // events per sub-batch of k_bucket
+constexpr int kTileBits = 11; // tile keys: K <= kMaxTiles < 2^11
+static_assert(kMaxTiles <= (1 << kTileBits), "tile key bits");
 
 // Bijection blockIdx -> work index that gives each XCD a contiguous range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
@@ -244,7 +246,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
         gbase[k] = row[k];
 
     const uint32_t tmask = (1u << tile_log) - 1u;
-    const int kbits = key_bits_for((uint32_t)K);
     const int64_t t_ref = ev.t[0];
     const int64_t u_lo = unit * E;
     const int64_t u_hi = min(u_lo + E, ev.n);
@@ -257,9 +258,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
         for (int k = lane; k < K; k += kWave)
             mycw[k] = 0;
         wave_sync();
-        const int64_t lo = sb + (int64_t)wave * PER_WAVE;
-        const int64_t hi = min(sb + SUB, u_hi);
-        int64_t t_carry = (lo > 0 && lo - 1 < ev.n) ? ev.t[lo - 1] : INT64_MIN;
+        // this sub-batch's events: [sb, sb + nsb); this wave's: from sb + w0
+        const int nsb = (int)min((int64_t)SUB, u_hi - sb);
+        const int w0 = wave * PER_WAVE;
+        const uint16_t* xb = ev.x + sb;
+        const uint16_t* yb = ev.y + sb;
+        const int64_t* tb = ev.t + sb;
+        const int8_t* pb = ev.p + sb;
+        int64_t t_carry = (sb + w0 > 0 && w0 < nsb) ? ev.t[sb + w0 - 1] : INT64_MIN;
         uint64_t recs[STEPS];
         uint32_t packed[STEPS];  // rank | tile << 16, or ~0 for no event
 #pragma unroll
@@ -269,25 +275,28 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
             int ps[BATCH];
 #pragma unroll
             for (int s = 0; s < BATCH; ++s) {
-                // clamped index, no select on the loaded values: all loads of
-                // the batch stay in flight together
-                const int64_t i = max(min(lo + (b0 + s) * kWave + lane, hi - 1), (int64_t)0);
-                xs[s] = ev.x[i];
-                ys[s] = ev.y[i];
-                ts[s] = ev.t[i];
-                ps[s] = ev.p[i];
+                // clamped 32-bit offset, no select on the loaded values: all
+                // loads of the batch stay in flight together
+                const int o = min(w0 + (b0 + s) * kWave + lane, nsb - 1);
+                xs[s] = xb[o];
+                ys[s] = yb[o];
+                ts[s] = tb[o];
+                ps[s] = pb[o];
             }
 #pragma unroll
             for (int s = 0; s < BATCH; ++s) {
-                const int64_t i = lo + (b0 + s) * kWave + lane;
-                const bool in = i < hi;
-                uint32_t q = 0;
-                const bool ok = in && valid_q(xs[s], ys[s], W, H, q);
+                const bool in = w0 + (b0 + s) * kWave + lane < nsb;
+                const uint32_t q = __umul24(ys[s], (uint32_t)W) + xs[s];
+                const bool ok = in && xs[s] < (uint32_t)W && ys[s] < (uint32_t)H;
                 const int64_t t = ts[s];
-                // decreasing time versus the previous event in array order
-                int64_t tprev = __shfl_up(t, 1);
-                if (lane == 0)
-                    tprev = t_carry;
+                // decreasing time versus the previous event in array order:
+                // the previous lane's time (lane 0: the previous step's last)
+                const uint64_t tu = (uint64_t)t, cu = (uint64_t)t_carry;
+                const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(
+                    (int)(uint32_t)cu, (int)(uint32_t)tu, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+                const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(
+                    (int)(uint32_t)(cu >> 32), (int)(uint32_t)(tu >> 32), 0x138, 0xF, 0xF, false);
+                const int64_t tprev = (int64_t)(((uint64_t)phi << 32) | plo);
                 if (in && t < tprev)
                     flags |= 1u;  // ESI_DIAG_UNSORTED
                 t_carry = __shfl(t, kWave - 1);
@@ -295,7 +304,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
                 if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
                     flags |= 4u;  // ESI_DIAG_TIME_RANGE
                 const uint32_t key = ok ? (q >> tile_log) : 0u;
-                const uint32_t rank = wave_stable_rank(ok, key, kbits, mycw);
+                const uint32_t rank = wave_stable_rank<kTileBits>(ok, key, mycw);
                 packed[b0 + s] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
                 recs[b0 + s] = pack_record(dt, q & tmask, ps[s] > 0);
             }

@@ -143,19 +143,19 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // Stable multisplit rank inside one wave step.  Lane l holds an element with
-// key `key` < 2^key_bits (valid when `ok`); lanes are in array order.
+// key `key` < 2^KEY_BITS (valid when `ok`); lanes are in array order.
 // Returns, for valid lanes, counter[key] (before this step) plus the number of
 // lower valid lanes with the same key, and advances counter[key] by the
 // number of valid lanes with that key.  The lanes sharing a key are found by
 // matching the key one bit at a time with ballots (a wave-wide match), so the
 // ranks are stable without atomics.
-template <typename CounterT>
-__device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, int key_bits,
-                                                     CounterT* counter)
+template <int KEY_BITS, typename CounterT>
+__device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, CounterT* counter)
 {
     const uint32_t lane = __lane_id();
     uint64_t peers = __ballot(ok);
-    for (int bit = 0; bit < key_bits; ++bit) {
+#pragma unroll
+    for (int bit = 0; bit < KEY_BITS; ++bit) {
         const bool lb = (key >> bit) & 1u;
         const uint64_t bm = __ballot(lb);
         peers &= lb ? bm : ~bm;
@@ -204,13 +204,5 @@ __device__ __forceinline__ uint32_t wave_stable_rank_lds(bool ok, uint32_t key, 
     return rank;
 }
 
-// Bits needed for keys in [0, n).
-__host__ __device__ inline int key_bits_for(uint32_t n)
-{
-    int b = 0;
-    while (b < 32 && (1u << b) < n)
-        ++b;
-    return b;
-}
 
 }  // namespace esi

@@ -56,6 +56,7 @@ constexpr uint64_t kLpxMask = (uint64_t)0x7FFF << 48;
 template <int PPT>
 struct TileCfg {
     static constexpr int TILE = kBlock * PPT;
+    static constexpr int TILE_BITS = PPT == 1 ? 8 : PPT == 2 ? 9 : PPT == 4 ? 10 : 11;
     // records per chunk: LDS holds them three times over (records, states,
     // frame indices) next to the (pixel, wave) counters of the tile; at one
     // pixel per thread five workgroups share a CU
@@ -161,9 +162,9 @@ __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& 
         const float Ff = (float)F;
         if (FULL || in[i]) {
             if (OUT & 1)
-                frow[l] = Ff;
+                __builtin_nontemporal_store(Ff, frow + l);
             if (OUT & 2)
-                urow[l] = frame_code(Ff);
+                __builtin_nontemporal_store(frame_code(Ff), urow + l);
         }
     }
 }
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     static_assert(kFrameGroup <= kBlock, "one frame time per thread");
     static_assert(PER_WAVE % kWave == 0, "chunk size");
     static_assert(CHUNK < 65536, "16-bit counters");
+    static_assert((1 << Cfg::TILE_BITS) == TILE, "tile key bits");
     __shared__ uint64_t sorted[CHUNK];    // records sorted by pixel (frame index over the pixel field)
     __shared__ double ktvs[CHUNK];        // k (t - t_first) of the sorted records; then
     double* chg_S = ktvs;                 // change lists: S / (s_max - s_min) after the change
@@ -305,7 +307,6 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     const int tile = blockIdx.x;
     const int64_t q0 = (int64_t)tile * TILE + tid;
     const int64_t npix = st.npix;
-    const int kbits = key_bits_for((uint32_t)TILE);
     const int nf = fo.nf;
     const int mode = walk_mode(mp, fo, (int64_t)(tile + 1) * TILE <= npix);
 
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                 if (kLdsRank)
                     rank[s] = wave_stable_rank_lds(c_ < cn, key, cnt[wave], rslot[wave], rseq);
                 else
-                    rank[s] = wave_stable_rank(c_ < cn, key, kbits, cnt[wave]);
+                    rank[s] = wave_stable_rank<Cfg::TILE_BITS>(c_ < cn, key, cnt[wave]);
             }
         }
         __syncthreads();

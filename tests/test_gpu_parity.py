@@ -255,3 +255,72 @@ def test_workload_sampled(esi, name, fps, sel):
     assert_state(stg, o, DEFAULT["C"], name)
     assert_frames(fg, fo, DEFAULT, name)
     assert diag["accepted"] == s.n - o.dropped
+
+
+def test_clamp_range_without_zero(esi):
+    """Clamp bounds that exclude 0: a decayed state leaves [s_min, s_max]
+    (and the initial S = 0 is outside), so frames clamp the decayed value."""
+    s = evgen.random_stream(seed=18, width=300, height=5, n=60_000, t_max=1_000_000,
+                            burst_frac=0.2)
+    tf = np.arange(1, 101, dtype=np.int64) * 10_000
+    for prm in (dict(C=0.2, k_per_us=2e-6, b=2.0, s_min=0.05, s_max=0.9),
+                dict(C=0.2, k_per_us=2e-6, b=1.0, s_min=-0.9, s_max=-0.1, flags=1)):
+        _check(esi, s, prm, tf, u8=True, where=f"clamp {prm['s_min']}..{prm['s_max']}")
+
+
+def _blob_state(blob, npix):
+    """S (= hi + lo), T, N, P from an exported state (40-byte header)."""
+    off = 40
+    hi = np.frombuffer(blob, np.float32, npix, off)
+    lo = np.frombuffer(blob, np.float32, npix, off + 4 * npix)
+    T = np.frombuffer(blob, np.int64, npix, off + 8 * npix)
+    N = np.frombuffer(blob, np.uint32, npix, off + 16 * npix)
+    P = np.frombuffer(blob, np.int32, npix, off + 20 * npix)
+    return hi.astype(np.float64) + lo.astype(np.float64), T, N, P
+
+
+def test_imported_state_outside_clamp(esi):
+    """A state imported from a call with wider clamps holds S outside
+    [s_min, s_max]: frames of pixels no later event touches must still clamp."""
+    W, H = 70, 40
+    s = evgen.random_stream(seed=19, width=W, height=H, n=80_000, t_max=400_000,
+                            burst_frac=0.5)
+    s.p[:] = 1  # every event +1: S grows well past 1 without a clamp
+    wide = dict(C=0.5, k_per_us=1e-6, b=2.0, s_min=-1e30, s_max=1e30)
+    narrow = dict(C=0.5, k_per_us=1e-6, b=2.0, s_min=-1.0, s_max=1.0)
+    a = esi.State(W, H, **wide)
+    a.integrate(s.x, s.y, s.t, s.p)
+    blob = a.export_state()
+    a.close()
+    S0, T0, N0, P0 = _blob_state(blob, W * H)
+    assert S0.max() > 1.5  # the case under test
+    b = esi.State(W, H, **narrow)
+    b.import_state(blob)
+    later = evgen.random_stream(seed=20, width=W, height=H, n=2_000, t_max=900_000,
+                                t_min=400_000)
+    tf = np.array([450_000, 700_000, 1_000_000, 2_000_000], np.int64)
+    fg, _ = b.integrate(later.x, later.y, later.t, later.p, t_frames=tf)
+    fg = fg.cpu().numpy()
+    o = oracle.State(W, H, oracle.Params(**narrow))
+    o.S[:], o.T[:], o.N[:], o.P[:] = S0, T0, N0, P0
+    fo = o.integrate(later.x, later.y, later.t, later.p, t_frames=tf)
+    assert_frames(fg, fo, narrow, "imported")
+    b.close()
+
+
+def test_u8_only_frames(esi):
+    """8-bit codes without FP32 frames equal the codes written next to them."""
+    s = evgen.random_stream(seed=21, width=257, height=9, n=100_000, t_max=1_000_000)
+    tf = np.arange(1, 51, dtype=np.int64) * 20_000
+    for prm in (DEFAULT, dict(DEFAULT, flags=2)):
+        a = esi.State(s.width, s.height, **prm)
+        f, u_both = a.integrate(s.x, s.y, s.t, s.p, t_frames=tf, want_u8=True)
+        b = esi.State(s.width, s.height, **prm)
+        none, u_only = b.integrate(s.x, s.y, s.t, s.p, t_frames=tf, want_frames=False,
+                                   want_u8=True)
+        assert none is None
+        np.testing.assert_array_equal(u_both.cpu().numpy(), u_only.cpu().numpy())
+        fo, _ = oracle_run(s, prm, t_frames=tf)
+        assert_u8(u_only.cpu().numpy(), fo, prm, "u8-only")
+        a.close()
+        b.close()

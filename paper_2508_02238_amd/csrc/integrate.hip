@@ -60,7 +60,7 @@ struct TileCfg {
     // records per chunk: LDS holds them three times over (records, states,
     // frame indices) next to the (pixel, wave) counters of the tile; at one
     // pixel per thread five workgroups share a CU
-    static constexpr int CHUNK = PPT == 2 ? 1280 : 1024;
+    static constexpr int CHUNK = PPT <= 2 ? 1280 : 1024;
     static constexpr int PER_WAVE = CHUNK / kWavesPerBlock;  // records per wave per chunk
     static constexpr int STEPS = PER_WAVE / kWave;           // records per lane per chunk
 };
@@ -283,6 +283,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     constexpr int PER_WAVE = Cfg::PER_WAVE;
     constexpr int STEPS = Cfg::STEPS;
     static_assert(kFrameGroup <= kBlock, "one frame time per thread");
+    static_assert(kFrameGroup < 128, "segment frame index in 7 bits");
     static_assert(PER_WAVE % kWave == 0, "chunk size");
     static_assert(CHUNK < 65536, "16-bit counters");
     static_assert((1 << Cfg::TILE_BITS) == TILE, "tile key bits");
@@ -496,7 +497,14 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                     const uint32_t at = (uint32_t)cnt[wave][record_lpx(rr[s]) & (TILE - 1)] + (rank[s] & 0xFFFFu);
                     if (at < cn) {
                         sorted[at] = (rr[s] & ~kLpxMask) | ((uint64_t)(rank[s] >> 16) << 48);
-                        ktvs[at] = mp.k * (double)(record_dt(rr[s]) - dt_first);
+                        // k (t - t_first) with the frame index and the
+                        // polarity in its 8 lowest mantissa bits (a relative
+                        // change below 2^-44)
+                        const double kt = mp.k * (double)(record_dt(rr[s]) - dt_first);
+                        const uint64_t kb = ((uint64_t)__double_as_longlong(kt) & ~(uint64_t)0xFF) |
+                                            (uint64_t)(rank[s] >> 16) |
+                                            ((uint64_t)record_pos(rr[s]) << 7);
+                        ktvs[at] = __longlong_as_double((long long)kb);
                     } else {
                         bad = true;
                     }
@@ -522,38 +530,40 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                 const uint32_t beg = min((uint32_t)cnt[0][l], end);
                 double S = px.S[i];
                 double A = __fma_rn(mp.k, (double)(px.T[i] - c.t_first), 1.0);
-                uint64_t r_prev = 0;
                 uint32_t w = beg, npos = 0;
                 int jc_prev = nfw;  // frame of the events applied so far (nfw: none)
                 for (uint32_t e = beg; e < end; ++e) {
-                    const uint64_t r = sorted[e];
                     const double kt = ktvs[e];
-                    const int jc = (int)record_lpx(r);
+                    const uint32_t low = (uint32_t)__double_as_longlong(kt);
+                    const int jc = (int)(low & 0x7Fu);
+                    const uint32_t pos = (low >> 7) & 1u;
                     if (jc != jc_prev && jc_prev < nfw) {
+                        // the group of event e - 1 is complete
+                        const uint64_t rp = sorted[e - 1];
                         chg_S[w] = S * mp.inv_range;
-                        chg_A[w] = __fma_rn(mp.k, (double)(t_ref + record_dt(r_prev) - tb), 1.0);
+                        chg_A[w] = __fma_rn(mp.k, (double)(t_ref + record_dt(rp) - tb), 1.0);
                         chg_j[w + l] = (uint16_t)jc_prev;
                         ++w;
                     }
                     jc_prev = jc;
                     const double u = fmin(fmax(A - kt, 0.0), 1.0);
                     const double d = power_b<BK>(u, mp.b);
-                    const int pos = record_pos(r);
                     const double s = pos ? mp.C : -mp.C;
                     S = clamp_s(mp, mp.decay_then_add ? __fma_rn(S, d, s) : (S + s) * d);
                     A = 1.0 + kt;
-                    npos += (uint32_t)pos;
-                    r_prev = r;
+                    npos += pos;
                 }
-                if (jc_prev < nfw) {
-                    chg_S[w] = S * mp.inv_range;
-                    chg_A[w] = __fma_rn(mp.k, (double)(t_ref + record_dt(r_prev) - tb), 1.0);
-                    chg_j[w + l] = (uint16_t)jc_prev;
-                    ++w;
+                if (end > beg) {
+                    const uint64_t rl = sorted[end - 1];  // the run's last event
+                    if (jc_prev < nfw) {
+                        chg_S[w] = S * mp.inv_range;
+                        chg_A[w] = __fma_rn(mp.k, (double)(t_ref + record_dt(rl) - tb), 1.0);
+                        chg_j[w + l] = (uint16_t)jc_prev;
+                        ++w;
+                    }
+                    px.T[i] = t_ref + record_dt(rl);
                 }
                 px.S[i] = S;
-                if (end > beg)
-                    px.T[i] = t_ref + record_dt(r_prev);
                 px.N[i] += end - beg;
                 px.P[i] += 2 * (int32_t)npos - (int32_t)(end - beg);
                 chg_j[w + l] = 0xFFFF;  // end of the list

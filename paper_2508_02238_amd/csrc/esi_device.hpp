@@ -1,11 +1,12 @@
-// esi_device.hpp -- device-side arithmetic of ESI shared by the kernels.
+// esi_device.hpp -- device-side arithmetic and wave primitives shared by the
+// kernels.
 //
 // Per event (Alg. 2, event loop): S <- (S + p C) d(dt), T <- t, S <- clamp(S)
-// with d(dt) = max(1 - k dt, 0)^b (Eq. (4)) and the clamp of Eq. (13).
-// All of it runs in FP64 in registers: on CDNA4 an FP64 FMA issues at the
-// same rate as an unpacked FP32 one, and FP64 keeps long runs of decay
-// factors close to 1 well inside a 1e-5 relative error without compensated
-// FP32 arithmetic.  Frames (Eq. (14)) are rounded to FP32 once, at the end.
+// with d(dt) = max(1 - k dt, 0)^b (Eq. (4)) and the clamp of Eq. (13).  The
+// kernels run it in FP64 registers: on CDNA4 an FP64 FMA issues at the same
+// rate as an unpacked FP32 one, and FP64 keeps long runs of decay factors
+// close to 1 well inside a 1e-5 relative error without compensated FP32
+// arithmetic.  Frames (Eq. (14)) are rounded to FP32 once, at the end.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,22 +58,6 @@ __device__ __forceinline__ double clamp_s(const MethodParams& mp, double s)
     return fmin(fmax(s, mp.s_min), mp.s_max);
 }
 
-// One event of Alg. 2 at a pixel whose state is (S, T, N, P).
-template <int BK>
-__device__ __forceinline__ void apply_event(const MethodParams& mp, double& S, int64_t& T,
-                                            uint32_t& N, int32_t& P, int64_t t, int pos)
-{
-    int64_t dt = t - T;
-    dt = dt < 0 ? 0 : dt;
-    const double d = decay<BK>(mp, dt);
-    const double s = pos ? mp.C : -mp.C;
-    const double v = mp.decay_then_add ? __fma_rn(S, d, s) : (S + s) * d;
-    S = clamp_s(mp, v);
-    T = t;
-    N += 1u;
-    P += pos ? 1 : -1;
-}
-
 // Eq. (14) of the state seen at t_f (decayed to t_f unless lazy), in [0, 1].
 template <int BK>
 __device__ __forceinline__ float frame_value(const MethodParams& mp, double S, int64_t T,
@@ -83,19 +68,6 @@ __device__ __forceinline__ float frame_value(const MethodParams& mp, double S, i
         int64_t dt = t_f - T;
         dt = dt < 0 ? 0 : dt;
         v = clamp_s(mp, S * decay<BK>(mp, dt));
-    }
-    return (float)((v - mp.s_min) * mp.inv_range);
-}
-
-// The same value from u = 1 - k (t_f - T) (not clipped), as the frame loop
-// keeps it: d = min(max(u, 0), 1)^b (u > 1 only when t_f < T: dt = 0).
-template <int BK>
-__device__ __forceinline__ float frame_value_u(const MethodParams& mp, double S, double u)
-{
-    double v = S;
-    if (!mp.lazy) {
-        const double uc = fmin(u, 1.0);
-        v = clamp_s(mp, (uc > 0.0) ? S * power_b<BK>(uc, mp.b) : 0.0);
     }
     return (float)((v - mp.s_min) * mp.inv_range);
 }

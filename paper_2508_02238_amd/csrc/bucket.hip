@@ -43,8 +43,6 @@ namespace {
 constexpr int kXcds = 8;
 constexpr int kSegRows = 16;  // table rows (ranges) per segment of the column scan
 constexpr int kSub = 2048;    // events per sub-batch of k_bucket
-constexpr int kTileBits = 11; // tile keys: K <= kMaxTiles < 2^11
-static_assert(kMaxTiles <= (1 << kTileBits), "tile key bits");
 
 // Bijection blockIdx -> work index that gives each XCD a contiguous range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
@@ -234,6 +232,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
     uint32_t* gbase = (uint32_t*)(staged + SUB);  // [K] next bucket position of each tile
     uint16_t* cw = (uint16_t*)(gbase + K);        // [4][K] per-wave counters, then run starts
     uint16_t* skey = cw + kWavesPerBlock * K;     // [SUB] tile of each staged record
+    uint8_t* rep = (uint8_t*)(skey + SUB);        // [4][K] representative lane per tile
     __shared__ uint32_t scan_w[kWavesPerBlock];
     __shared__ uint32_t sub_total;
 
@@ -250,6 +249,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
     const int64_t u_lo = unit * E;
     const int64_t u_hi = min(u_lo + E, ev.n);
     uint16_t* mycw = cw + wave * K;
+    uint8_t* myrep = rep + wave * K;
     uint32_t flags = 0;
     bool bad = false;
 
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
                 if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
                     flags |= 4u;  // ESI_DIAG_TIME_RANGE
                 const uint32_t key = ok ? (q >> tile_log) : 0u;
-                const uint32_t rank = wave_stable_rank<kTileBits>(ok, key, mycw);
+                const uint32_t rank = wave_stable_rank_rep(ok, key, mycw, myrep);
                 packed[b0 + s] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
                 recs[b0 + s] = pack_record(dt, q & tmask, ps[s] > 0);
             }
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
 size_t bucket_lds(int K)
 {
     return sizeof(uint64_t) * kSub + sizeof(uint32_t) * K +
-           sizeof(uint16_t) * (kWavesPerBlock * K + kSub);
+           sizeof(uint16_t) * (kWavesPerBlock * K + kSub) + kWavesPerBlock * (size_t)K;
 }
 
 }  // namespace

@@ -142,6 +142,39 @@ __device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, Coun
     return base + r;
 }
 
+// The same rank for keys with many bits: the lanes first agree on one
+// representative lane per distinct key (each lane writes its lane number to
+// slot[key], one write per key survives and every lane reads it back), so
+// that the match runs on the 6-bit representative instead of the key.
+// slot: one byte per key, no initialisation needed (every key present in the
+// step is written in the step before it is read).
+template <typename CounterT>
+__device__ __forceinline__ uint32_t wave_stable_rank_rep(bool ok, uint32_t key, CounterT* counter,
+                                                         uint8_t* slot)
+{
+    const uint32_t lane = __lane_id();
+    if (ok)
+        slot[key] = (uint8_t)lane;
+    wave_sync();
+    const uint32_t rep = ok ? (uint32_t)slot[key] : 0u;
+    wave_sync();
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 6; ++bit) {
+        const bool lb = (rep >> bit) & 1u;
+        const uint64_t bm = __ballot(lb);
+        peers &= lb ? bm : ~bm;
+    }
+    const uint32_t r = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+    const uint32_t c = (uint32_t)__popcll(peers);
+    const uint32_t base = ok ? (uint32_t)counter[key] : 0u;
+    wave_sync();  // every lane has read its counter before the update
+    if (ok && r + 1u == c)
+        counter[key] = (CounterT)(base + c);  // the last lane of each key group
+    wave_sync();
+    return base + r;
+}
+
 // The same stable rank through LDS, in rounds: in each round every valid lane
 // not ranked yet posts a priority for its key with an atomic max, and the
 // lowest lane of each key (the highest priority) takes counter[key] and

@@ -97,25 +97,46 @@ struct Pixels {
     int32_t P[PPT];
     // the state the frames see: Sv = S / (s_max - s_min) and Av = 1 + k (T - t_b)
     double Sv[PPT], Av[PPT];
-    // change list of the segment: next entry to load
-    uint32_t nx[PPT];
-    int jn[PPT];              // segment frame of the next change (>= kFrameGroup: none)
-    double Sn[PPT], An[PPT];  // its state
+    // change list of the segment: byte offsets of the next change's entry in
+    // chg_S / chg_A (8-byte entries) and of the frame index after it in chg_j
+    // (2-byte entries)
+    uint32_t eo[PPT], jo[PPT];
+    int jn[PPT];  // segment frame of the next change (>= kFrameGroup: none)
 };
 
-// Load the next change of pixel slot i.  Pixel l's frame indices sit at
+// Take the next change of pixel slot i: its state becomes the visible one and
+// the frame of the change after it is read.  Pixel l's frame indices sit at
 // chg_j[entry + l] and are followed by a 0xFFFF sentinel, so no test of the
-// list's end is needed; states are read at a clamped index.
-template <int PPT, int CH>
-__device__ __forceinline__ void next_change(Pixels<PPT>& px, int i, int l, const double* chg_S,
+// list's end is needed.
+template <int PPT>
+__device__ __forceinline__ void take_change(Pixels<PPT>& px, int i, const double* chg_S,
                                             const double* chg_A, const uint16_t* chg_j)
 {
-    const uint32_t e = min(px.nx[i], (uint32_t)(CH - 1));
-    px.Sn[i] = chg_S[e];
-    px.An[i] = chg_A[e];
-    px.jn[i] = chg_j[px.nx[i] + l];
-    ++px.nx[i];
+    px.Sv[i] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(chg_S) + px.eo[i]);
+    px.Av[i] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(chg_A) + px.eo[i]);
+    px.jn[i] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(chg_j) + px.jo[i]);
+    px.eo[i] += 8u;
+    px.jo[i] += 2u;
 }
+
+// A lane's double, read by the whole wave (l uniform).
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFF), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Buffer resource for one frame row piece of `bytes` bytes: stores at or past
+// `bytes` (pixel slots off the sensor in the last tile) are dropped by the
+// buffer range check.  Word 3 is the gfx9 raw-buffer format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void* row, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(row, (short)0, (int)bytes, 0x00020000);
+}
+
+constexpr int kNontemporal = 2;  // cache policy of the frame stores: streaming
 
 // One frame (index jj of the segment) of Eq. (14): take the pixel's next
 // change if it belongs to this frame, then
@@ -125,24 +146,18 @@ __device__ __forceinline__ void next_change(Pixels<PPT>& px, int i, int l, const
 // F = (v - s_min) / (s_max - s_min).  CLAMP: the clamp of Eq. (13) on the
 // decayed value, a no-op when s_min <= 0 <= s_max and the state is in range
 // (then Sv u^b lies between 0 and Sv).  OUT: 1 FP32 frames, 2 8-bit codes,
-// 3 both.  FULL: every pixel slot of the tile is on the sensor.
-template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT, bool FULL, int CH>
+// 3 both; fr / ur: this frame's row piece of the tile.
+template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT>
 __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& px, int jj, double kt,
                                            const double* chg_S, const double* chg_A,
-                                           const uint16_t* chg_j, float* frow, uint8_t* urow,
-                                           const bool (&in)[PPT])
+                                           const uint16_t* chg_j, __amdgpu_buffer_rsrc_t fr,
+                                           __amdgpu_buffer_rsrc_t ur)
 {
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int l = (int)threadIdx.x + i * kBlock;
-        if (px.jn[i] == jj) {
-            px.Sv[i] = px.Sn[i];
-            px.Av[i] = px.An[i];
-            // keep the loads below the moves, so that they can land in the
-            // registers of Sn / An themselves (no copies on the other path)
-            __builtin_amdgcn_sched_barrier(0);
-            next_change<PPT, CH>(px, i, l, chg_S, chg_A, chg_j);
-        }
+        if (px.jn[i] == jj)
+            take_change<PPT>(px, i, chg_S, chg_A, chg_j);
         double F;
         if (LAZY) {
             F = px.Sv[i] + mp.f_off;
@@ -160,84 +175,78 @@ __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& 
             }
         }
         const float Ff = (float)F;
-        if (FULL || in[i]) {
-            if (OUT & 1)
-                __builtin_nontemporal_store(Ff, frow + l);
-            if (OUT & 2)
-                __builtin_nontemporal_store(frame_code(Ff), urow + l);
-        }
+        if (OUT & 1)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(Ff), fr, l * 4, 0, kNontemporal);
+        if (OUT & 2)
+            __builtin_amdgcn_raw_buffer_store_b8(frame_code(Ff), ur, l, 0, kNontemporal);
     }
 }
 
-// Phase B over the nfw frames of one segment; frow / urow point at the
-// tile's piece of the segment's first frame; ktl[jj] = k (t_f - t_b), read
-// two frames at a time one pair ahead.
-template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT, bool FULL, int CH>
-__device__ __forceinline__ void walk_segment(const MethodParams& mp, Pixels<PPT>& px, int nfw,
-                                             const double* ktl, const double* chg_S,
-                                             const double* chg_A, const uint16_t* chg_j,
-                                             float* frow, uint8_t* urow, int64_t npix,
-                                             const bool (&in)[PPT])
+// Phase B over frames [jj0, jj1) of one segment (at most 64: kt of frame jj
+// is lane jj - jj0 of ktv); frow / urow point at the tile's piece of frame
+// jj0 (`fbytes` / `ubytes` of it on the sensor) and advance.
+template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT>
+__device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>& px, int jj0, int jj1,
+                                            double ktv, const double* chg_S, const double* chg_A,
+                                            const uint16_t* chg_j, float*& frow, uint8_t*& urow,
+                                            int64_t npix, uint32_t fbytes, uint32_t ubytes)
 {
-    const double2* kt2 = reinterpret_cast<const double2*>(ktl);
-    double2 kk = kt2[0];
-    for (int jj = 0; jj < nfw; jj += 2) {
-        const double2 cur = kk;
-        kk = kt2[min(jj / 2 + 1, kFrameGroup / 2 - 1)];
-        frame_step<PPT, BK, LAZY, CLAMP, OUT, FULL, CH>(mp, px, jj, cur.x, chg_S, chg_A, chg_j,
-                                                        frow, urow, in);
+    for (int jj = jj0; jj < jj1; ++jj) {
+        const double kt = LAZY ? 0.0 : lane_value(ktv, jj - jj0);
+        const __amdgpu_buffer_rsrc_t fr = row_rsrc((OUT & 1) ? (void*)frow : nullptr, fbytes);
+        const __amdgpu_buffer_rsrc_t ur = row_rsrc((OUT & 2) ? (void*)urow : nullptr, ubytes);
+        frame_step<PPT, BK, LAZY, CLAMP, OUT>(mp, px, jj, kt, chg_S, chg_A, chg_j, fr, ur);
         if (OUT & 1)
             frow += npix;
         if (OUT & 2)
             urow += npix;
-        if (jj + 1 < nfw) {
-            frame_step<PPT, BK, LAZY, CLAMP, OUT, FULL, CH>(mp, px, jj + 1, cur.y, chg_S, chg_A,
-                                                            chg_j, frow, urow, in);
-            if (OUT & 1)
-                frow += npix;
-            if (OUT & 2)
-                urow += npix;
-        }
     }
 }
 
-// Output mode of a call: 0-2 decayed snapshots (FP32, 8-bit, both), 3-5 the
-// same with the clamp, 6-8 lazy; +9 for a tile with pixel slots off the sensor.
-__device__ __forceinline__ int walk_mode(const MethodParams& mp, const FrameOut& fo, bool full)
+// Phase B over the nfw frames of one segment; ktv0 / ktv1 hold k (t_f - t_b)
+// of frames lane and 64 + lane.
+template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT>
+__device__ __forceinline__ void walk_segment(const MethodParams& mp, Pixels<PPT>& px, int nfw,
+                                             double ktv0, double ktv1, const double* chg_S,
+                                             const double* chg_A, const uint16_t* chg_j,
+                                             float* frow, uint8_t* urow, int64_t npix,
+                                             uint32_t fbytes, uint32_t ubytes)
 {
-    const int out = (fo.frames && fo.frames_u8) ? 2 : (fo.frames ? 0 : 1);
-    return (mp.lazy ? 6 : (mp.need_clamp ? 3 : 0)) + out + (full ? 0 : 9);
+    walk_frames<PPT, BK, LAZY, CLAMP, OUT>(mp, px, 0, min(nfw, kWave), ktv0, chg_S, chg_A, chg_j,
+                                           frow, urow, npix, fbytes, ubytes);
+    if (nfw > kWave)
+        walk_frames<PPT, BK, LAZY, CLAMP, OUT>(mp, px, kWave, nfw, ktv1, chg_S, chg_A, chg_j, frow,
+                                               urow, npix, fbytes, ubytes);
 }
 
-template <int PPT, int BK, int CH>
-__device__ __forceinline__ void walk_dispatch(int mode, const MethodParams& mp, Pixels<PPT>& px,
-                                              int nfw, const double* ktl, const double* chg_S,
-                                              const double* chg_A, const uint16_t* chg_j,
-                                              float* frow, uint8_t* urow, int64_t npix,
-                                              const bool (&in)[PPT])
+// Output mode of a call: 0-2 decayed snapshots (FP32, 8-bit, both), 3-5 the
+// same with the clamp, 6-8 lazy.
+__device__ __forceinline__ int walk_mode(const MethodParams& mp, const FrameOut& fo)
 {
-#define ESI_WALK(L, C, O, F)                                                                   \
-    walk_segment<PPT, BK, L, C, O, F, CH>(mp, px, nfw, ktl, chg_S, chg_A, chg_j, frow, urow, \
-                                          npix, in)
+    const int out = (fo.frames && fo.frames_u8) ? 2 : (fo.frames ? 0 : 1);
+    return (mp.lazy ? 6 : (mp.need_clamp ? 3 : 0)) + out;
+}
+
+template <int PPT, int BK>
+__device__ __forceinline__ void walk_dispatch(int mode, const MethodParams& mp, Pixels<PPT>& px,
+                                              int nfw, double ktv0, double ktv1,
+                                              const double* chg_S, const double* chg_A,
+                                              const uint16_t* chg_j, float* frow, uint8_t* urow,
+                                              int64_t npix, uint32_t fbytes, uint32_t ubytes)
+{
+#define ESI_WALK(L, C, O)                                                                     \
+    walk_segment<PPT, BK, L, C, O>(mp, px, nfw, ktv0, ktv1, chg_S, chg_A, chg_j, frow, urow, \
+                                   npix, fbytes, ubytes)
     switch (mode) {
-    case 0: ESI_WALK(false, false, 1, true); break;
-    case 1: ESI_WALK(false, false, 2, true); break;
-    case 2: ESI_WALK(false, false, 3, true); break;
-    case 3: ESI_WALK(false, true, 1, true); break;
-    case 4: ESI_WALK(false, true, 2, true); break;
-    case 5: ESI_WALK(false, true, 3, true); break;
-    case 6: ESI_WALK(true, false, 1, true); break;
-    case 7: ESI_WALK(true, false, 2, true); break;
-    case 8: ESI_WALK(true, false, 3, true); break;
-    case 9: ESI_WALK(false, false, 1, false); break;
-    case 10: ESI_WALK(false, false, 2, false); break;
-    case 11: ESI_WALK(false, false, 3, false); break;
-    case 12: ESI_WALK(false, true, 1, false); break;
-    case 13: ESI_WALK(false, true, 2, false); break;
-    case 14: ESI_WALK(false, true, 3, false); break;
-    case 15: ESI_WALK(true, false, 1, false); break;
-    case 16: ESI_WALK(true, false, 2, false); break;
-    default: ESI_WALK(true, false, 3, false); break;
+    case 0: ESI_WALK(false, false, 1); break;
+    case 1: ESI_WALK(false, false, 2); break;
+    case 2: ESI_WALK(false, false, 3); break;
+    case 3: ESI_WALK(false, true, 1); break;
+    case 4: ESI_WALK(false, true, 2); break;
+    case 5: ESI_WALK(false, true, 3); break;
+    case 6: ESI_WALK(true, false, 1); break;
+    case 7: ESI_WALK(true, false, 2); break;
+    default: ESI_WALK(true, false, 3); break;
     }
 #undef ESI_WALK
 }
@@ -287,8 +296,9 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     static_assert(PER_WAVE % kWave == 0, "chunk size");
     static_assert(CHUNK < 65536, "16-bit counters");
     static_assert((1 << Cfg::TILE_BITS) == TILE, "tile key bits");
-    __shared__ uint64_t sorted[CHUNK];    // records sorted by pixel (frame index over the pixel field)
-    __shared__ double ktvs[CHUNK];        // k (t - t_first) of the sorted records; then
+    // (one spare entry each: the change lists' reads one past a last entry)
+    __shared__ uint64_t sorted[CHUNK + 1];  // records sorted by pixel (frame index over the pixel field)
+    __shared__ double ktvs[CHUNK + 1];      // k (t - t_first) of the sorted records; then
     double* chg_S = ktvs;                 // change lists: S / (s_max - s_min) after the change
     __shared__ uint16_t chg_j[CHUNK + TILE];  // change lists: frame index in the segment
     __shared__ uint16_t cnt[kWavesPerBlock][TILE];
@@ -297,7 +307,6 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     constexpr bool kLdsRank = PPT <= 2;
     __shared__ uint32_t rslot[kWavesPerBlock][kLdsRank ? TILE : 1];
     __shared__ int64_t tfl[kFrameGroup];  // frame times of the segment
-    __shared__ __align__(16) double ktl[kFrameGroup];  // k (t_f - t_b) of the segment's frames
     __shared__ uint32_t scan_w[kWavesPerBlock];
     __shared__ uint32_t cut_w[kWavesPerBlock];
     double* chg_A = reinterpret_cast<double*>(sorted);  // change lists: A after the change
@@ -309,7 +318,9 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     const int64_t q0 = (int64_t)tile * TILE + tid;
     const int64_t npix = st.npix;
     const int nf = fo.nf;
-    const int mode = walk_mode(mp, fo, (int64_t)(tile + 1) * TILE <= npix);
+    const int mode = walk_mode(mp, fo);
+    // pixels of the tile on the sensor: the frame stores' range
+    const uint32_t tile_px = (uint32_t)min((int64_t)TILE, npix - (int64_t)tile * TILE);
 
     Pixels<PPT> px;
     bool in[PPT];
@@ -407,10 +418,8 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
 
         // the segment's frame times; the visible state before this chunk's
         // events
-        if (tid < kFrameGroup) {
+        if (tid < kFrameGroup)
             tfl[tid] = tfv;
-            ktl[tid] = mp.k * (double)(tfv - tb);
-        }
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             px.Sv[i] = px.S[i] * mp.inv_range;
@@ -433,6 +442,10 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             }
         }
         __syncthreads();
+        // decay bases k (t_f - t_b) of the segment's frames, one per lane:
+        // frames lane and 64 + lane
+        const double ktv0 = mp.k * (double)(tfl[lane] - tb);
+        const double ktv1 = mp.k * (double)(tfl[min(kWave + lane, kFrameGroup - 1)] - tb);
         int j_end = jmax;
         if (search)
             j_end = j + frames_before(tfl, jmax - j, c.t_after);
@@ -567,8 +580,11 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                 px.N[i] += end - beg;
                 px.P[i] += 2 * (int32_t)npos - (int32_t)(end - beg);
                 chg_j[w + l] = 0xFFFF;  // end of the list
-                px.nx[i] = beg;
-                next_change<PPT, CHUNK>(px, i, l, chg_S, chg_A, chg_j);
+                // the first change's frame; eo at its entry, jo at the frame
+                // index after it
+                px.jn[i] = chg_j[beg + (uint32_t)l];
+                px.eo[i] = 8u * beg;
+                px.jo[i] = 2u * (beg + (uint32_t)l + 1u);
             }
         } else {
 #pragma unroll
@@ -583,9 +599,10 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
         // 4. phase B: the frames this chunk completes
         if (nfw > 0) {
             const size_t base = (size_t)j * (size_t)npix + (size_t)tile * TILE;
-            walk_dispatch<PPT, BK, CHUNK>(mode, mp, px, nfw, ktl, chg_S, chg_A, chg_j,
-                                          fo.frames ? fo.frames + base : nullptr,
-                                          fo.frames_u8 ? fo.frames_u8 + base : nullptr, npix, in);
+            walk_dispatch<PPT, BK>(mode, mp, px, nfw, ktv0, ktv1, chg_S, chg_A, chg_j,
+                                   fo.frames ? fo.frames + base : nullptr,
+                                   fo.frames_u8 ? fo.frames_u8 + base : nullptr, npix,
+                                   4u * tile_px, tile_px);
         }
         j = j_end;
         cs = ce;

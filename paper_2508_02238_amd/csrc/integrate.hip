@@ -191,7 +191,6 @@ __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>&
                                             const uint16_t* chg_j, float*& frow, uint8_t*& urow,
                                             int64_t npix, uint32_t fbytes, uint32_t ubytes)
 {
-#pragma unroll 2
     for (int jj = jj0; jj < jj1; ++jj) {
         const double kt = LAZY ? 0.0 : lane_value(ktv, jj - jj0);
         const __amdgpu_buffer_rsrc_t fr = row_rsrc((OUT & 1) ? (void*)frow : nullptr, fbytes);

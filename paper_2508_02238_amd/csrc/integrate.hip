@@ -510,13 +510,13 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                     const uint32_t at = (uint32_t)cnt[wave][record_lpx(rr[s]) & (TILE - 1)] + (rank[s] & 0xFFFFu);
                     if (at < cn) {
                         sorted[at] = (rr[s] & ~kLpxMask) | ((uint64_t)(rank[s] >> 16) << 48);
-                        // k (t - t_first) with the frame index and the
-                        // polarity in its 8 lowest mantissa bits (a relative
-                        // change below 2^-44)
+                        // k (t - t_first) with the frame index and a
+                        // negative-polarity bit in its 8 lowest mantissa bits
+                        // (a relative change below 2^-44)
                         const double kt = mp.k * (double)(record_dt(rr[s]) - dt_first);
                         const uint64_t kb = ((uint64_t)__double_as_longlong(kt) & ~(uint64_t)0xFF) |
                                             (uint64_t)(rank[s] >> 16) |
-                                            ((uint64_t)record_pos(rr[s]) << 7);
+                                            ((uint64_t)(record_pos(rr[s]) ^ 1u) << 7);
                         ktvs[at] = __longlong_as_double((long long)kb);
                     } else {
                         bad = true;
@@ -532,10 +532,18 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             // the event A = 1 + kt.  N, P and T are settled once per run.
             // The change list keeps, per segment frame jc that first includes
             // some event, the state after the last such event, written once
-            // the next event belongs to a later frame (or the run ends).
-            // Entries go over the pixel's own slots of `sorted`/`ktvs`, behind
-            // the read position.  Events after the segment (jc == nfw) make
-            // no entry.
+            // the next event belongs to a later frame (or the run ends); its
+            // decay base is A + k (t_first - t_b).  Entries go over the
+            // pixel's own slots of `sorted`/`ktvs`, behind the read position
+            // (an entry written at event e lands at or before e - 1, while the
+            // loop has already read e + 1).  Events after the segment
+            // (jc == nfw) make no entry.
+            const double dA = mp.k * (double)(c.t_first - tb);
+            const uint64_t c_bits = (uint64_t)__double_as_longlong(mp.C);
+            const uint32_t c_hi = (uint32_t)(c_bits >> 32), c_lo = (uint32_t)c_bits;
+            // clamp bounds in canonical form once, not on every event
+            const double s_min = __builtin_canonicalize(mp.s_min);
+            const double s_max = __builtin_canonicalize(mp.s_max);
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 const int l = tid + i * kBlock;
@@ -543,34 +551,47 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                 const uint32_t beg = min((uint32_t)cnt[0][l], end);
                 double S = px.S[i];
                 double A = __fma_rn(mp.k, (double)(px.T[i] - c.t_first), 1.0);
-                uint32_t w = beg, npos = 0;
+                uint32_t w = beg, nneg = 0;
                 int jc_prev = nfw;  // frame of the events applied so far (nfw: none)
-                for (uint32_t e = beg; e < end; ++e) {
-                    const double kt = ktvs[e];
-                    const uint32_t low = (uint32_t)__double_as_longlong(kt);
-                    const int jc = (int)(low & 0x7Fu);
-                    const uint32_t pos = (low >> 7) & 1u;
-                    if (jc != jc_prev && jc_prev < nfw) {
-                        // the group of event e - 1 is complete
-                        const uint64_t rp = sorted[e - 1];
-                        chg_S[w] = S * mp.inv_range;
-                        chg_A[w] = __fma_rn(mp.k, (double)(t_ref + record_dt(rp) - tb), 1.0);
-                        chg_j[w + l] = (uint16_t)jc_prev;
-                        ++w;
+                auto run = [&](auto decay_then_add) {
+                    // the next event's kt is read one iteration ahead
+                    // (indices up to end <= CHUNK: the spare entry)
+                    double kt_next = ktvs[beg];
+                    for (uint32_t e = beg; e < end; ++e) {
+                        const double kt = kt_next;
+                        kt_next = ktvs[e + 1];
+                        const uint32_t low = (uint32_t)__double_as_longlong(kt);
+                        const int jc = (int)(low & 0x7Fu);
+                        const uint32_t neg = (low >> 7) & 1u;
+                        if (jc != jc_prev && jc_prev < nfw) {
+                            // the group of event e - 1 is complete
+                            chg_S[w] = S * mp.inv_range;
+                            chg_A[w] = A + dA;
+                            chg_j[w + l] = (uint16_t)jc_prev;
+                            ++w;
+                        }
+                        jc_prev = jc;
+                        const double u = fmin(fmax(A - kt, 0.0), 1.0);
+                        const double d = power_b<BK>(u, mp.b);
+                        // +C or -C: the polarity flips the sign bit of C
+                        const double s = __hiloint2double((int)(c_hi + (neg << 31)), (int)c_lo);
+                        if constexpr (decltype(decay_then_add)::value)
+                            S = fmin(fmax(__fma_rn(S, d, s), s_min), s_max);
+                        else
+                            S = fmin(fmax((S + s) * d, s_min), s_max);
+                        A = 1.0 + kt;
+                        nneg += neg;
                     }
-                    jc_prev = jc;
-                    const double u = fmin(fmax(A - kt, 0.0), 1.0);
-                    const double d = power_b<BK>(u, mp.b);
-                    const double s = pos ? mp.C : -mp.C;
-                    S = clamp_s(mp, mp.decay_then_add ? __fma_rn(S, d, s) : (S + s) * d);
-                    A = 1.0 + kt;
-                    npos += pos;
-                }
+                };
+                if (mp.decay_then_add)
+                    run(std::true_type{});
+                else
+                    run(std::false_type{});
                 if (end > beg) {
                     const uint64_t rl = sorted[end - 1];  // the run's last event
                     if (jc_prev < nfw) {
                         chg_S[w] = S * mp.inv_range;
-                        chg_A[w] = __fma_rn(mp.k, (double)(t_ref + record_dt(rl) - tb), 1.0);
+                        chg_A[w] = A + dA;
                         chg_j[w + l] = (uint16_t)jc_prev;
                         ++w;
                     }
@@ -578,7 +599,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
                 }
                 px.S[i] = S;
                 px.N[i] += end - beg;
-                px.P[i] += 2 * (int32_t)npos - (int32_t)(end - beg);
+                px.P[i] += (int32_t)(end - beg) - 2 * (int32_t)nneg;
                 chg_j[w + l] = 0xFFFF;  // end of the list
                 // the first change's frame; eo at its entry, jo at the frame
                 // index after it

@@ -233,6 +233,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
     uint16_t* cw = (uint16_t*)(gbase + K);        // [4][K] per-wave counters, then run starts
     uint16_t* skey = cw + kWavesPerBlock * K;     // [SUB] tile of each staged record
     uint8_t* rep = (uint8_t*)(skey + SUB);        // [4][K] representative lane per tile
+    __shared__ uint64_t group[kWavesPerBlock][kWave];  // lane masks of the rank
     __shared__ uint32_t scan_w[kWavesPerBlock];
     __shared__ uint32_t sub_total;
 
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
                 if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
                     flags |= 4u;  // ESI_DIAG_TIME_RANGE
                 const uint32_t key = ok ? (q >> tile_log) : 0u;
-                const uint32_t rank = wave_stable_rank_rep(ok, key, mycw, myrep);
+                const uint32_t rank = wave_stable_rank_or(ok, key, mycw, myrep, group[wave]);
                 packed[b0 + s] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
                 recs[b0 + s] = pack_record(dt, q & tmask, ps[s] > 0);
             }

@@ -142,72 +142,37 @@ __device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, Coun
     return base + r;
 }
 
-// The same rank for keys with many bits: the lanes first agree on one
-// representative lane per distinct key (each lane writes its lane number to
-// slot[key], one write per key survives and every lane reads it back), so
-// that the match runs on the 6-bit representative instead of the key.
-// slot: one byte per key, no initialisation needed (every key present in the
-// step is written in the step before it is read).
+// The same rank with the key's lanes found through LDS: the lanes of a key
+// agree on a representative lane (each writes its lane number to slot[key],
+// one write per key survives), clear the representative's word of `group`,
+// and OR their own lane bits into it; the word then holds the key's lane
+// mask.  OR is order-independent, so the result does not depend on how LDS
+// serialises lanes that hit one word.  slot: one byte per key, group: 64
+// words; neither needs initialisation.
 template <typename CounterT>
-__device__ __forceinline__ uint32_t wave_stable_rank_rep(bool ok, uint32_t key, CounterT* counter,
-                                                         uint8_t* slot)
+__device__ __forceinline__ uint32_t wave_stable_rank_or(bool ok, uint32_t key, CounterT* counter,
+                                                        uint8_t* slot, uint64_t* group)
 {
     const uint32_t lane = __lane_id();
     if (ok)
         slot[key] = (uint8_t)lane;
     wave_sync();
-    const uint32_t rep = ok ? (uint32_t)slot[key] : 0u;
-    wave_sync();
-    uint64_t peers = __ballot(ok);
-#pragma unroll
-    for (int bit = 0; bit < 6; ++bit) {
-        const bool lb = (rep >> bit) & 1u;
-        const uint64_t bm = __ballot(lb);
-        peers &= lb ? bm : ~bm;
+    uint32_t rep = 0, base = 0;
+    if (ok) {
+        rep = slot[key];
+        base = (uint32_t)counter[key];
+        group[rep] = 0;
+        __hip_atomic_fetch_or(&group[rep], 1ull << lane, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
+    wave_sync();
+    const uint64_t peers = ok ? group[rep] : 0ull;
     const uint32_t r = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
     const uint32_t c = (uint32_t)__popcll(peers);
-    const uint32_t base = ok ? (uint32_t)counter[key] : 0u;
-    wave_sync();  // every lane has read its counter before the update
     if (ok && r + 1u == c)
         counter[key] = (CounterT)(base + c);  // the last lane of each key group
     wave_sync();
     return base + r;
 }
-
-// The same stable rank through LDS, in rounds: in each round every valid lane
-// not ranked yet posts a priority for its key with an atomic max, and the
-// lowest lane of each key (the highest priority) takes counter[key] and
-// advances it; distinct keys in a round make those updates independent.
-// Priorities carry a round sequence number (`seq`, kept by the caller and
-// increasing across calls) in the high bits, so `slot` never needs clearing:
-// a later round's value always exceeds an earlier one.  A step costs one
-// round per lane of the most frequent key (usually one or two), against one
-// ballot per key bit in wave_stable_rank.  slot: one word per key, zeroed
-// once before the first call.
-template <typename CounterT>
-__device__ __forceinline__ uint32_t wave_stable_rank_lds(bool ok, uint32_t key, CounterT* counter,
-                                                         uint32_t* slot, uint32_t& seq)
-{
-    const uint32_t lane = __lane_id();
-    uint32_t rank = 0;
-    bool mine = ok;
-    while (__ballot(mine)) {
-        ++seq;
-        const uint32_t prio = (seq << 6) | (uint32_t)(kWave - 1 - lane);
-        if (mine)
-            atomicMax(&slot[key], prio);
-        wave_sync();
-        const bool win = mine && slot[key] == prio;
-        if (win) {
-            rank = (uint32_t)counter[key];
-            counter[key] = (CounterT)(rank + 1u);
-        }
-        wave_sync();
-        mine = mine && !win;
-    }
-    return rank;
-}
-
 
 }  // namespace esi

@@ -277,8 +277,9 @@ __device__ __forceinline__ ChunkCtl chunk_ctl(const uint64_t* records, uint32_t 
 
 // One pixel per thread: five workgroups per CU (at most 96 VGPRs, 32 KB of
 // LDS each), so that a 640x480 sensor's 1200 tiles are all resident at once.
+// Two pixels per thread: four (at most 128 VGPRs, 40 KB of LDS).
 template <int PPT>
-constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : 1; }
+constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : PPT == 2 ? 4 : 1; }
 
 template <int PPT, int BK>
 __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
@@ -302,10 +303,12 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     double* chg_S = ktvs;                 // change lists: S / (s_max - s_min) after the change
     __shared__ uint16_t chg_j[CHUNK + TILE];  // change lists: frame index in the segment
     __shared__ uint16_t cnt[kWavesPerBlock][TILE];
-    // rank priorities per (wave, pixel) for the LDS stable rank (one and two
-    // pixels per thread; larger tiles use the ballot rank)
-    constexpr bool kLdsRank = PPT <= 2;
-    __shared__ uint32_t rslot[kWavesPerBlock][kLdsRank ? TILE : 1];
+    // representative lane per (wave, pixel) and lane masks per wave for the
+    // LDS stable rank (one and two pixels per thread; larger tiles, whose
+    // threads hold more registers, use the ballot rank)
+    constexpr bool kOrRank = PPT <= 2;
+    __shared__ uint8_t rrep[kWavesPerBlock][kOrRank ? TILE : 1];
+    __shared__ uint64_t rgroup[kWavesPerBlock][kOrRank ? kWave : 1];
     __shared__ int64_t tfl[kFrameGroup];  // frame times of the segment
     __shared__ uint32_t scan_w[kWavesPerBlock];
     __shared__ uint32_t cut_w[kWavesPerBlock];
@@ -346,11 +349,6 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     int j = 0;  // first frame of the segment (uniform)
     uint32_t cs = rs;
     bool bad = false;
-    uint32_t rseq = 0;  // rank round sequence number of this wave
-    if (kLdsRank) {
-        for (int k = lane; k < TILE; k += kWave)
-            rslot[wave][k] = 0;
-    }
     ChunkCtl c = chunk_ctl<CHUNK>(records, cs, re, t_ref, fo, j);
 
     // records of the first chunk and the first frame times; clamped indices,
@@ -435,8 +433,8 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             for (int s = 0; s < STEPS; ++s) {
                 const uint32_t c_ = (uint32_t)(wave * PER_WAVE + s * kWave + lane);
                 const uint32_t key = record_lpx(rr[s]) & (TILE - 1);
-                if (kLdsRank)
-                    rank[s] = wave_stable_rank_lds(c_ < cn, key, cnt[wave], rslot[wave], rseq);
+                if (kOrRank)
+                    rank[s] = wave_stable_rank_or(c_ < cn, key, cnt[wave], rrep[wave], rgroup[wave]);
                 else
                     rank[s] = wave_stable_rank<Cfg::TILE_BITS>(c_ < cn, key, cnt[wave]);
             }

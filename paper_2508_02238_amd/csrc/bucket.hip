@@ -227,13 +227,19 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
     constexpr int STEPS = PER_WAVE / kWave;         // steps of 64 per wave
     constexpr int BATCH = STEPS < 8 ? STEPS : 8;    // steps loaded ahead
     static_assert(STEPS % BATCH == 0, "sub-batch size");
+    static_assert(sizeof(uint64_t) * SUB >= sizeof(uint64_t) * kWavesPerBlock * kWave +
+                                                kWavesPerBlock * kMaxTiles,
+                  "the rank's scratch fits the staging area");
     extern __shared__ uint64_t smem[];
+    // LDS: staged | cw | gbase | wd | skey.  While a sub-batch is ranked, the
+    // staging area holds the rank's representative lanes and lane masks.
     uint64_t* staged = smem;                      // [SUB] records of the sub-batch by tile
-    uint32_t* gbase = (uint32_t*)(staged + SUB);  // [K] next bucket position of each tile
-    uint16_t* cw = (uint16_t*)(gbase + K);        // [4][K] per-wave counters, then run starts
-    uint16_t* skey = cw + kWavesPerBlock * K;     // [SUB] tile of each staged record
-    uint8_t* rep = (uint8_t*)(skey + SUB);        // [4][K] representative lane per tile
-    __shared__ uint64_t group[kWavesPerBlock][kWave];  // lane masks of the rank
+    uint64_t* cw = staged + SUB;                  // [K] 4 x u16: per-wave counters, then run starts
+    uint32_t* gbase = (uint32_t*)(cw + K);        // [K] next bucket position of each tile
+    uint32_t* wd = gbase + K;                     // [K] bucket position minus staged position
+    uint16_t* skey = (uint16_t*)(wd + K);         // [SUB] tile of each staged record
+    uint64_t* group = staged;                     // [4][64] lane masks of the rank
+    uint8_t* rep = (uint8_t*)(staged + kWavesPerBlock * kWave);  // [4][K] representative lanes
     __shared__ uint32_t scan_w[kWavesPerBlock];
     __shared__ uint32_t sub_total;
 
@@ -242,23 +248,23 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
     const int lane = tid % kWave;
     const int64_t unit = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t* row = table + unit * K;
-    for (int k = tid; k < K; k += kBlock)
+    for (int k = tid; k < K; k += kBlock) {
         gbase[k] = row[k];
+        cw[k] = 0;
+    }
+    __syncthreads();
 
     const uint32_t tmask = (1u << tile_log) - 1u;
     const int64_t t_ref = ev.t[0];
     const int64_t u_lo = unit * E;
     const int64_t u_hi = min(u_lo + E, ev.n);
-    uint16_t* mycw = cw + wave * K;
+    uint16_t* mycw = (uint16_t*)cw + wave;
     uint8_t* myrep = rep + wave * K;
+    uint64_t* mygroup = group + wave * kWave;
     uint32_t flags = 0;
     bool bad = false;
 
     for (int64_t sb = u_lo; sb < u_hi; sb += SUB) {
-        // each wave clears its own counters
-        for (int k = lane; k < K; k += kWave)
-            mycw[k] = 0;
-        wave_sync();
         // this sub-batch's events: [sb, sb + nsb); this wave's: from sb + w0
         const int nsb = (int)min((int64_t)SUB, u_hi - sb);
         const int w0 = wave * PER_WAVE;
@@ -300,12 +306,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
                 const int64_t tprev = (int64_t)(((uint64_t)phi << 32) | plo);
                 if (in && t < tprev)
                     flags |= 1u;  // ESI_DIAG_UNSORTED
-                t_carry = __shfl(t, kWave - 1);
+                t_carry = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(tu >> 32), kWave - 1) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)tu, kWave - 1));
                 const int64_t dt = t - t_ref;
                 if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
                     flags |= 4u;  // ESI_DIAG_TIME_RANGE
                 const uint32_t key = ok ? (q >> tile_log) : 0u;
-                const uint32_t rank = wave_stable_rank_or(ok, key, mycw, myrep, group[wave]);
+                const uint32_t rank = wave_stable_rank_or<kWavesPerBlock>(ok, key, mycw, myrep, mygroup);
                 packed[b0 + s] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
                 recs[b0 + s] = pack_record(dt, q & tmask, ps[s] > 0);
             }
@@ -313,16 +320,20 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
         __syncthreads();
 
         // exclusive scan over (tile, wave), tile-major: start of each wave's
-        // run of each tile inside the sub-batch sorted by tile
+        // run of each tile inside the sub-batch sorted by tile; each tile's
+        // bucket position advances by its count here, and wd keeps the
+        // offset from staged to bucket position for this sub-batch
         {
             const int kpt = (K + kBlock - 1) / kBlock;  // tiles per thread, consecutive
             const int k0 = tid * kpt;
             uint32_t sum = 0;
             for (int kk = 0; kk < kpt; ++kk) {
                 const int k = k0 + kk;
-                if (k < K)
-                    for (int w = 0; w < kWavesPerBlock; ++w)
-                        sum += cw[w * K + k];
+                if (k < K) {
+                    const uint64_t v = cw[k];
+                    sum += (uint32_t)(v & 0xFFFF) + (uint32_t)((v >> 16) & 0xFFFF) +
+                           (uint32_t)((v >> 32) & 0xFFFF) + (uint32_t)(v >> 48);
+                }
             }
             uint32_t inc = sum;
 #pragma unroll
@@ -341,22 +352,30 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
                 sub_total = run + sum;
             for (int kk = 0; kk < kpt; ++kk) {
                 const int k = k0 + kk;
-                if (k < K)
+                if (k < K) {
+                    const uint64_t v = cw[k];
+                    const uint32_t s0 = run;
+                    uint64_t starts = 0;
+#pragma unroll
                     for (int w = 0; w < kWavesPerBlock; ++w) {
-                        const uint32_t c = cw[w * K + k];
-                        cw[w * K + k] = (uint16_t)run;
-                        run += c;
+                        starts |= (uint64_t)(run & 0xFFFFu) << (16 * w);
+                        run += (uint32_t)(v >> (16 * w)) & 0xFFFFu;
                     }
+                    cw[k] = starts;
+                    const uint32_t g0 = gbase[k];
+                    wd[k] = g0 - s0;
+                    gbase[k] = g0 + (run - s0);
+                }
             }
         }
         __syncthreads();
 
-        // stage the records in tile order
+        // stage the records in tile order (over the rank's scratch)
 #pragma unroll
         for (int s = 0; s < STEPS; ++s) {
             if (packed[s] != 0xFFFFFFFFu) {
                 const uint32_t key = packed[s] >> 16;
-                const uint32_t pos = (uint32_t)mycw[key] + (packed[s] & 0xFFFFu);
+                const uint32_t pos = (uint32_t)mycw[key * kWavesPerBlock] + (packed[s] & 0xFFFFu);
                 if (pos < (uint32_t)SUB) {
                     staged[pos] = recs[s];
                     skey[pos] = (uint16_t)key;
@@ -368,24 +387,20 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
         __syncthreads();
 
         // each tile's run of this sub-batch is appended to its bucket:
-        // consecutive staged records of one tile land on consecutive addresses
+        // consecutive staged records of one tile land on consecutive
+        // addresses; the counters are cleared for the next sub-batch
         const uint32_t total = min(sub_total, (uint32_t)SUB);
         for (uint32_t p = tid; p < total; p += kBlock) {
             const uint32_t k = skey[p];
-            const int64_t g = (int64_t)gbase[k] + (int64_t)(p - cw[k]);
-            if (k < (uint32_t)K && g >= 0 && g < cap)
+            const int64_t g = (k < (uint32_t)K) ? (int64_t)(uint32_t)(wd[k] + p) : -1;
+            if (g >= 0 && g < cap)
                 records[g] = staged[p];
             else
                 bad = true;
         }
-        __syncthreads();
-        // advance each tile's bucket position by its run length
-        for (int k = tid; k < K; k += kBlock) {
-            const uint32_t p0 = cw[k];
-            const uint32_t p1 = (k + 1 < K) ? (uint32_t)cw[k + 1] : total;
-            gbase[k] += (p1 > p0) ? p1 - p0 : 0u;
-        }
-        __syncthreads();  // staged and cw are reused by the next sub-batch
+        for (int k = tid; k < K; k += kBlock)
+            cw[k] = 0;
+        __syncthreads();  // staged, skey and cw are reused by the next sub-batch
     }
     if (bad)
         flags |= 8u;  // ESI_DIAG_INTERNAL: never expected
@@ -401,8 +416,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H
 
 size_t bucket_lds(int K)
 {
-    return sizeof(uint64_t) * kSub + sizeof(uint32_t) * K +
-           sizeof(uint16_t) * (kWavesPerBlock * K + kSub) + kWavesPerBlock * (size_t)K;
+    return sizeof(uint64_t) * (kSub + (size_t)K) + 2 * sizeof(uint32_t) * K +
+           sizeof(uint16_t) * kSub;
 }
 
 }  // namespace

@@ -148,8 +148,9 @@ __device__ __forceinline__ uint32_t wave_stable_rank(bool ok, uint32_t key, Coun
 // and OR their own lane bits into it; the word then holds the key's lane
 // mask.  OR is order-independent, so the result does not depend on how LDS
 // serialises lanes that hit one word.  slot: one byte per key, group: 64
-// words; neither needs initialisation.
-template <typename CounterT>
+// words; neither needs initialisation.  The counter of key k is
+// counter[k * STRIDE].
+template <int STRIDE = 1, typename CounterT>
 __device__ __forceinline__ uint32_t wave_stable_rank_or(bool ok, uint32_t key, CounterT* counter,
                                                         uint8_t* slot, uint64_t* group)
 {
@@ -160,7 +161,7 @@ __device__ __forceinline__ uint32_t wave_stable_rank_or(bool ok, uint32_t key, C
     uint32_t rep = 0, base = 0;
     if (ok) {
         rep = slot[key];
-        base = (uint32_t)counter[key];
+        base = (uint32_t)counter[key * STRIDE];
         group[rep] = 0;
         __hip_atomic_fetch_or(&group[rep], 1ull << lane, __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -170,7 +171,7 @@ __device__ __forceinline__ uint32_t wave_stable_rank_or(bool ok, uint32_t key, C
     const uint32_t r = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
     const uint32_t c = (uint32_t)__popcll(peers);
     if (ok && r + 1u == c)
-        counter[key] = (CounterT)(base + c);  // the last lane of each key group
+        counter[key * STRIDE] = (CounterT)(base + c);  // the last lane of each key group
     wave_sync();
     return base + r;
 }

@@ -59,8 +59,8 @@ struct TileCfg {
     static constexpr int TILE_BITS = PPT == 1 ? 8 : PPT == 2 ? 9 : PPT == 4 ? 10 : 11;
     // records per chunk: LDS holds them three times over (records, states,
     // frame indices) next to the (pixel, wave) counters of the tile; at one
-    // pixel per thread five workgroups share a CU
-    static constexpr int CHUNK = PPT <= 2 ? 1280 : 1024;
+    // pixel per thread five workgroups share a CU, at two four
+    static constexpr int CHUNK = PPT == 1 ? 1280 : PPT == 2 ? 1536 : 1024;
     static constexpr int PER_WAVE = CHUNK / kWavesPerBlock;  // records per wave per chunk
     static constexpr int STEPS = PER_WAVE / kWave;           // records per lane per chunk
 };
@@ -457,11 +457,29 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
         const ChunkCtl c1 = chunk_ctl<CHUNK>(records, ce, re, t_ref, fo, j_end);
 
         if (cn > 0) {
-            // 2b. the segment frame of each record, kept with its rank
+            // 2b. the segment frame of each record (the number of segment
+            // frames earlier than it; binary lifting with as many steps as
+            // the segment's frame count needs), kept with its rank
+            {
+                int jc[STEPS];
+                int64_t tr[STEPS];
 #pragma unroll
-            for (int s = 0; s < STEPS; ++s) {
-                const int jc = frames_before(tfl, nfw, t_ref + record_dt(rr[s]));
-                rank[s] |= (uint32_t)jc << 16;
+                for (int s = 0; s < STEPS; ++s) {
+                    jc[s] = 0;
+                    tr[s] = t_ref + record_dt(rr[s]);
+                }
+                const int top = nfw > 0 ? 1 << (31 - __clz(nfw)) : 0;
+                for (int step = top; step >= 1; step >>= 1) {
+#pragma unroll
+                    for (int s = 0; s < STEPS; ++s) {
+                        const int probe = jc[s] + step;
+                        const int64_t v = tfl[min(probe, nfw) - 1];
+                        jc[s] = (probe <= nfw && v < tr[s]) ? probe : jc[s];
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < STEPS; ++s)
+                    rank[s] |= (uint32_t)jc[s] << 16;
             }
             // 2c. exclusive scan over (pixel, wave), pixel-major
             {

@@ -257,6 +257,27 @@ def test_workload_sampled(esi, name, fps, sel):
     assert diag["accepted"] == s.n - o.dropped
 
 
+@pytest.mark.parametrize("W,H,prm", [
+    (1280, 720, DEFAULT),                   # 2 pixels per thread (1800 tiles)
+    (1600, 1000, PARAM_SWEEP[6]),           # 4 pixels per thread (1563 tiles)
+    (2000, 2000, PARAM_SWEEP[3]),           # 8 pixels per thread (1954 tiles)
+])
+def test_large_sensors(esi, W, H, prm):
+    """Sensors large enough for several pixels per thread (the ballot-ranked
+    tile sizes included): random events with same-time bursts and a few hot
+    pixels whose runs span many chunks; full state and sampled frames."""
+    s = evgen.hot_pixel_stream(seed=W + H, width=W, height=H, n_bg=1_500_000,
+                               t_max=1_000_000, hot=[(0, 0), (W - 1, H - 1), (W // 2, H // 3)],
+                               hot_period_us=97)
+    tf = np.arange(1, 21, dtype=np.int64) * 50_000
+    sel = [0, 7, 19]
+    fg, _, stg, diag = gpu_run(esi, s, prm, t_frames=tf, frame_sel=sel)
+    fo, o = oracle_run(s, prm, t_frames=tf, frame_sel=sel)
+    assert_state(stg, o, prm["C"], f"{W}x{H}")
+    assert_frames(fg, fo, prm, f"{W}x{H}")
+    assert diag["accepted"] == s.n - o.dropped
+
+
 def test_clamp_range_without_zero(esi):
     """Clamp bounds that exclude 0: a decayed state leaves [s_min, s_max]
     (and the initial S = 0 is outside), so frames clamp the decayed value."""

@@ -42,7 +42,7 @@ namespace {
 
 constexpr int kXcds = 8;
 constexpr int kSegRows = 16;  // table rows (ranges) per segment of the column scan
-constexpr int kSub = 2048;    // events per sub-batch of k_bucket
+constexpr int kSub = 4096;    // events per sub-batch of k_bucket
 
 // Bijection blockIdx -> work index that gives each XCD a contiguous range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int
 // ---- stable bucketing, staged in LDS ------------------------------------------
 
 template <int SUB>
-__global__ __launch_bounds__(kBlock, 4) void k_bucket(EventsDev ev, int W, int H, int tile_log,
+__global__ __launch_bounds__(kBlock, 2) void k_bucket(EventsDev ev, int W, int H, int tile_log,
                                                    int K, int64_t E, const uint32_t* table,
                                                    uint64_t* records, int64_t cap, DiagDev* diag)
 {

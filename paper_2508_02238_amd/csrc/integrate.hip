@@ -53,16 +53,19 @@ constexpr double kMaxSegmentDecay = 1073741824.0;   // 2^30
 constexpr int kNever = 0x7FFFFFFF;                  // "no further change"
 constexpr uint64_t kLpxMask = (uint64_t)0x7FFF << 48;
 
-template <int PPT>
+// A tile of NB * PPT pixels: NB threads, PPT pixels each (thread t holds
+// pixels t, t + NB, ...).
+template <int PPT, int NB>
 struct TileCfg {
-    static constexpr int TILE = kBlock * PPT;
-    static constexpr int TILE_BITS = PPT == 1 ? 8 : PPT == 2 ? 9 : PPT == 4 ? 10 : 11;
+    static constexpr int TILE = NB * PPT;
+    static constexpr int WAVES = NB / kWave;
+    static constexpr int TILE_BITS = TILE == 256 ? 8 : TILE == 512 ? 9 : TILE == 1024 ? 10 : 11;
     // records per chunk: LDS holds them three times over (records, states,
-    // frame indices) next to the (pixel, wave) counters of the tile; at one
-    // pixel per thread five workgroups share a CU, at two four
+    // frame indices) next to the (pixel, wave) counters of the tile; five
+    // workgroups share a CU at one pixel per thread, four at two
     static constexpr int CHUNK = PPT == 1 ? 1280 : PPT == 2 ? 1536 : 1024;
-    static constexpr int PER_WAVE = CHUNK / kWavesPerBlock;  // records per wave per chunk
-    static constexpr int STEPS = PER_WAVE / kWave;           // records per lane per chunk
+    static constexpr int PER_WAVE = CHUNK / WAVES;  // records per wave per chunk
+    static constexpr int STEPS = PER_WAVE / kWave;  // records per lane per chunk
 };
 
 struct FrameOut {
@@ -147,7 +150,7 @@ constexpr int kNontemporal = 2;  // cache policy of the frame stores: streaming
 // decayed value, a no-op when s_min <= 0 <= s_max and the state is in range
 // (then Sv u^b lies between 0 and Sv).  OUT: 1 FP32 frames, 2 8-bit codes,
 // 3 both; fr / ur: this frame's row piece of the tile.
-template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT>
+template <int PPT, int NB, int BK, bool LAZY, bool CLAMP, int OUT>
 __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& px, int jj, double kt,
                                            const double* chg_S, const double* chg_A,
                                            const uint16_t* chg_j, __amdgpu_buffer_rsrc_t fr,
@@ -155,7 +158,7 @@ __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& 
 {
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int l = (int)threadIdx.x + i * kBlock;
+        const int l = (int)threadIdx.x + i * NB;
         if (px.jn[i] == jj)
             take_change<PPT>(px, i, chg_S, chg_A, chg_j);
         double F;
@@ -185,7 +188,7 @@ __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& 
 // Phase B over frames [jj0, jj1) of one segment (at most 64: kt of frame jj
 // is lane jj - jj0 of ktv); frow / urow point at the tile's piece of frame
 // jj0 (`fbytes` / `ubytes` of it on the sensor) and advance.
-template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT>
+template <int PPT, int NB, int BK, bool LAZY, bool CLAMP, int OUT>
 __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>& px, int jj0, int jj1,
                                             double ktv, const double* chg_S, const double* chg_A,
                                             const uint16_t* chg_j, float*& frow, uint8_t*& urow,
@@ -195,7 +198,7 @@ __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>&
         const double kt = LAZY ? 0.0 : lane_value(ktv, jj - jj0);
         const __amdgpu_buffer_rsrc_t fr = row_rsrc((OUT & 1) ? (void*)frow : nullptr, fbytes);
         const __amdgpu_buffer_rsrc_t ur = row_rsrc((OUT & 2) ? (void*)urow : nullptr, ubytes);
-        frame_step<PPT, BK, LAZY, CLAMP, OUT>(mp, px, jj, kt, chg_S, chg_A, chg_j, fr, ur);
+        frame_step<PPT, NB, BK, LAZY, CLAMP, OUT>(mp, px, jj, kt, chg_S, chg_A, chg_j, fr, ur);
         if (OUT & 1)
             frow += npix;
         if (OUT & 2)
@@ -205,18 +208,18 @@ __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>&
 
 // Phase B over the nfw frames of one segment; ktv0 / ktv1 hold k (t_f - t_b)
 // of frames lane and 64 + lane.
-template <int PPT, int BK, bool LAZY, bool CLAMP, int OUT>
+template <int PPT, int NB, int BK, bool LAZY, bool CLAMP, int OUT>
 __device__ __forceinline__ void walk_segment(const MethodParams& mp, Pixels<PPT>& px, int nfw,
                                              double ktv0, double ktv1, const double* chg_S,
                                              const double* chg_A, const uint16_t* chg_j,
                                              float* frow, uint8_t* urow, int64_t npix,
                                              uint32_t fbytes, uint32_t ubytes)
 {
-    walk_frames<PPT, BK, LAZY, CLAMP, OUT>(mp, px, 0, min(nfw, kWave), ktv0, chg_S, chg_A, chg_j,
-                                           frow, urow, npix, fbytes, ubytes);
+    walk_frames<PPT, NB, BK, LAZY, CLAMP, OUT>(mp, px, 0, min(nfw, kWave), ktv0, chg_S, chg_A,
+                                               chg_j, frow, urow, npix, fbytes, ubytes);
     if (nfw > kWave)
-        walk_frames<PPT, BK, LAZY, CLAMP, OUT>(mp, px, kWave, nfw, ktv1, chg_S, chg_A, chg_j, frow,
-                                               urow, npix, fbytes, ubytes);
+        walk_frames<PPT, NB, BK, LAZY, CLAMP, OUT>(mp, px, kWave, nfw, ktv1, chg_S, chg_A, chg_j,
+                                                   frow, urow, npix, fbytes, ubytes);
 }
 
 // Output mode of a call: 0-2 decayed snapshots (FP32, 8-bit, both), 3-5 the
@@ -227,7 +230,7 @@ __device__ __forceinline__ int walk_mode(const MethodParams& mp, const FrameOut&
     return (mp.lazy ? 6 : (mp.need_clamp ? 3 : 0)) + out;
 }
 
-template <int PPT, int BK>
+template <int PPT, int NB, int BK>
 __device__ __forceinline__ void walk_dispatch(int mode, const MethodParams& mp, Pixels<PPT>& px,
                                               int nfw, double ktv0, double ktv1,
                                               const double* chg_S, const double* chg_A,
@@ -235,7 +238,7 @@ __device__ __forceinline__ void walk_dispatch(int mode, const MethodParams& mp, 
                                               int64_t npix, uint32_t fbytes, uint32_t ubytes)
 {
 #define ESI_WALK(L, C, O)                                                                     \
-    walk_segment<PPT, BK, L, C, O>(mp, px, nfw, ktv0, ktv1, chg_S, chg_A, chg_j, frow, urow, \
+    walk_segment<PPT, NB, BK, L, C, O>(mp, px, nfw, ktv0, ktv1, chg_S, chg_A, chg_j, frow, urow, \
                                    npix, fbytes, ubytes)
     switch (mode) {
     case 0: ESI_WALK(false, false, 1); break;
@@ -277,22 +280,25 @@ __device__ __forceinline__ ChunkCtl chunk_ctl(const uint64_t* records, uint32_t 
 
 // One pixel per thread: five workgroups per CU (at most 96 VGPRs, 32 KB of
 // LDS each), so that a 640x480 sensor's 1200 tiles are all resident at once.
-// Two pixels per thread: four (at most 128 VGPRs, 40 KB of LDS).
-template <int PPT>
+// Two pixels per thread: four (at most 128 VGPRs, 40 KB).  (Tiles of 512
+// pixels as 512 threads x 1 pixel ran 7% slower than 256 x 2 on the
+// 1280x720 spoke workload: two workgroups per CU, eight-wave barriers.)
+template <int PPT, int NB>
 constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : PPT == 2 ? 4 : 1; }
 
-template <int PPT, int BK>
-__global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
+template <int PPT, int NB, int BK>
+__global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrate(
     const uint64_t* __restrict__ records, const uint32_t* __restrict__ table,
     const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t, int K, StateDev st,
     MethodParams mp, FrameOut fo, DiagDev* diag)
 {
-    using Cfg = TileCfg<PPT>;
+    using Cfg = TileCfg<PPT, NB>;
     constexpr int TILE = Cfg::TILE;
+    constexpr int WAVES = Cfg::WAVES;
     constexpr int CHUNK = Cfg::CHUNK;
     constexpr int PER_WAVE = Cfg::PER_WAVE;
     constexpr int STEPS = Cfg::STEPS;
-    static_assert(kFrameGroup <= kBlock, "one frame time per thread");
+    static_assert(kFrameGroup <= NB, "one frame time per thread");
     static_assert(kFrameGroup < 128, "segment frame index in 7 bits");
     static_assert(PER_WAVE % kWave == 0, "chunk size");
     static_assert(CHUNK < 65536, "16-bit counters");
@@ -302,16 +308,16 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     __shared__ double ktvs[CHUNK + 1];      // k (t - t_first) of the sorted records; then
     double* chg_S = ktvs;                 // change lists: S / (s_max - s_min) after the change
     __shared__ uint16_t chg_j[CHUNK + TILE];  // change lists: frame index in the segment
-    __shared__ uint16_t cnt[kWavesPerBlock][TILE];
+    __shared__ uint16_t cnt[WAVES][TILE];
     // representative lane per (wave, pixel) and lane masks per wave for the
     // LDS stable rank (one and two pixels per thread; larger tiles, whose
     // threads hold more registers, use the ballot rank)
     constexpr bool kOrRank = PPT <= 2;
-    __shared__ uint8_t rrep[kWavesPerBlock][kOrRank ? TILE : 1];
-    __shared__ uint64_t rgroup[kWavesPerBlock][kOrRank ? kWave : 1];
+    __shared__ uint8_t rrep[WAVES][kOrRank ? TILE : 1];
+    __shared__ uint64_t rgroup[WAVES][kOrRank ? kWave : 1];
     __shared__ int64_t tfl[kFrameGroup];  // frame times of the segment
-    __shared__ uint32_t scan_w[kWavesPerBlock];
-    __shared__ uint32_t cut_w[kWavesPerBlock];
+    __shared__ uint32_t scan_w[WAVES];
+    __shared__ uint32_t cut_w[WAVES];
     double* chg_A = reinterpret_cast<double*>(sorted);  // change lists: A after the change
 
     const int tid = threadIdx.x;
@@ -329,7 +335,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     bool in[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int64_t q = q0 + (int64_t)i * kBlock;
+        const int64_t q = q0 + (int64_t)i * NB;
         in[i] = q < npix;
         px.S[i] = in[i] ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
         px.T[i] = in[i] ? st.T[q] : 0;
@@ -397,8 +403,10 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             if (lane == 0)
                 cut_w[wave] = first;
             __syncthreads();
-            cn = min(min(cut_w[0], cut_w[1]), min(cut_w[2], cut_w[3]));
-            cn = min(cn, c.avail);
+            cn = c.avail;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w)
+                cn = min(cn, cut_w[w]);
         }
         const uint32_t ce = cs + cn;
         // frames the chunk completes: all of the segment unless the record
@@ -483,12 +491,12 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             }
             // 2c. exclusive scan over (pixel, wave), pixel-major
             {
-                uint32_t v[PPT][kWavesPerBlock];
+                uint32_t v[PPT][WAVES];
                 uint32_t sum = 0;
 #pragma unroll
                 for (int i = 0; i < PPT; ++i)
 #pragma unroll
-                    for (int w = 0; w < kWavesPerBlock; ++w) {
+                    for (int w = 0; w < WAVES; ++w) {
                         v[i][w] = cnt[w][tid * PPT + i];
                         sum += v[i][w];
                     }
@@ -508,7 +516,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
 #pragma unroll
                 for (int i = 0; i < PPT; ++i)
 #pragma unroll
-                    for (int w = 0; w < kWavesPerBlock; ++w) {
+                    for (int w = 0; w < WAVES; ++w) {
                         cnt[w][tid * PPT + i] = (uint16_t)run;
                         run += v[i][w];
                     }
@@ -562,7 +570,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
             const double s_max = __builtin_canonicalize(mp.s_max);
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
-                const int l = tid + i * kBlock;
+                const int l = tid + i * NB;
                 const uint32_t end = min((l + 1 < TILE) ? (uint32_t)cnt[0][l + 1] : cn, cn);
                 const uint32_t beg = min((uint32_t)cnt[0][l], end);
                 double S = px.S[i];
@@ -636,7 +644,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
         // 4. phase B: the frames this chunk completes
         if (nfw > 0) {
             const size_t base = (size_t)j * (size_t)npix + (size_t)tile * TILE;
-            walk_dispatch<PPT, BK>(mode, mp, px, nfw, ktv0, ktv1, chg_S, chg_A, chg_j,
+            walk_dispatch<PPT, NB, BK>(mode, mp, px, nfw, ktv0, ktv1, chg_S, chg_A, chg_j,
                                    fo.frames ? fo.frames + base : nullptr,
                                    fo.frames_u8 ? fo.frames_u8 + base : nullptr, npix,
                                    4u * tile_px, tile_px);
@@ -653,7 +661,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
 
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int64_t q = q0 + (int64_t)i * kBlock;
+        const int64_t q = q0 + (int64_t)i * NB;
         if (in[i]) {
             const float hi = (float)px.S[i];
             st.S_hi[q] = hi;
@@ -668,7 +676,7 @@ __global__ __launch_bounds__(kBlock, min_blocks_per_cu<PPT>()) void k_integrate(
     // frame times must be non-decreasing; the first workgroup checks
     if (tile == 0) {
         bool unsorted = false;
-        for (int jj = 1 + tid; jj < nf; jj += kBlock)
+        for (int jj = 1 + tid; jj < nf; jj += NB)
             unsorted |= fo.t_frames[jj] < fo.t_frames[jj - 1];
         if (unsorted)
             atomicOr(&diag->flags, 2u);  // ESI_DIAG_FRAMES_UNSORTED
@@ -709,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void k_reset(StateDev st, int64_t t0, DiagD
 
 int decay_kind(double b) { return b == 1.0 ? kDecayB1 : (b == 2.0 ? kDecayB2 : kDecayPow); }
 
-template <int PPT, int BK>
+template <int PPT, int NB, int BK>
 hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                               const CallScratch& cs, const MethodParams& mp,
                               const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
@@ -717,13 +725,13 @@ hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Sch
 {
     FrameOut fo{t_frames, nf, frames, frames_u8};
     const bool has = ev.n > 0;
-    hipLaunchKernelGGL((k_integrate<PPT, BK>), dim3(sc.ntiles), dim3(kBlock), 0, stream,
+    hipLaunchKernelGGL((k_integrate<PPT, NB, BK>), dim3(sc.ntiles), dim3(NB), 0, stream,
                        has ? cs.records : nullptr, has ? cs.table : nullptr,
                        has ? cs.total : nullptr, has ? ev.t : nullptr, sc.ntiles, st, mp, fo, diag);
     return hipGetLastError();
 }
 
-template <int PPT>
+template <int PPT, int NB>
 hipError_t launch_integrate_p(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                               const CallScratch& cs, const MethodParams& mp,
                               const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
@@ -731,13 +739,13 @@ hipError_t launch_integrate_p(const EventsDev& ev, const StateDev& st, const Sch
 {
     switch (decay_kind(mp.b)) {
     case kDecayB1:
-        return launch_integrate_t<PPT, kDecayB1>(ev, st, sc, cs, mp, t_frames, nf, frames,
+        return launch_integrate_t<PPT, NB, kDecayB1>(ev, st, sc, cs, mp, t_frames, nf, frames,
                                                  frames_u8, diag, stream);
     case kDecayB2:
-        return launch_integrate_t<PPT, kDecayB2>(ev, st, sc, cs, mp, t_frames, nf, frames,
+        return launch_integrate_t<PPT, NB, kDecayB2>(ev, st, sc, cs, mp, t_frames, nf, frames,
                                                  frames_u8, diag, stream);
     default:
-        return launch_integrate_t<PPT, kDecayPow>(ev, st, sc, cs, mp, t_frames, nf, frames,
+        return launch_integrate_t<PPT, NB, kDecayPow>(ev, st, sc, cs, mp, t_frames, nf, frames,
                                                   frames_u8, diag, stream);
     }
 }
@@ -750,14 +758,19 @@ hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Sched
                             DiagDev* diag, hipStream_t stream)
 {
     switch (sc.ppt) {
+    // 256 threads per tile, 1, 2, 4 or 8 pixels each
     case 1:
-        return launch_integrate_p<1>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
+        return launch_integrate_p<1, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
+                                          stream);
     case 2:
-        return launch_integrate_p<2>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
+        return launch_integrate_p<2, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
+                                          stream);
     case 4:
-        return launch_integrate_p<4>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
+        return launch_integrate_p<4, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
+                                          stream);
     case 8:
-        return launch_integrate_p<8>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag, stream);
+        return launch_integrate_p<8, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
+                                          stream);
     default:
         return hipErrorInvalidValue;
     }

@@ -47,7 +47,7 @@ namespace {
 
 // s_waitcnt immediate (gfx9 encoding): vmcnt = 0, expcnt and lgkmcnt not waited.
 constexpr int kWaitVmcnt0 = 0x0F70;
-constexpr int kFrameGroup = 96;                     // frames per segment, at most
+constexpr int kFrameGroup = 112;                    // frames per segment, at most
 constexpr int kSearchTop = 64;                      // largest power of two <= kFrameGroup
 constexpr double kMaxSegmentDecay = 1073741824.0;   // 2^30
 constexpr int kNever = 0x7FFFFFFF;                  // "no further change"

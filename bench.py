@@ -34,12 +34,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(n: int, npix: int, nf: int, u8: bool) -> int:
+def algorithmic_bytes(n: int, npix: int, nf: int, u8: bool, f32: bool = True) -> int:
     """Bytes the method itself must move in one whole-stream call: the events
     read once (x, y u16, t i64, p i8 = 13 B), the per-pixel state read and
     written once (S f32, T i64, N u32, P i32 = 20 B each way), every frame
-    written once (4 B per pixel, plus 1 B with 8-bit codes)."""
-    return 13 * n + 40 * npix + (4 + (1 if u8 else 0)) * nf * npix
+    written once (4 B per pixel as FP32, 1 B as 8-bit codes)."""
+    return 13 * n + 40 * npix + ((4 if f32 else 0) + (1 if u8 else 0)) * nf * npix
 
 
 def measured_traffic(workload: str, fps: float):
@@ -72,6 +72,9 @@ def main() -> int:
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--fps", type=float, default=100.0)
     ap.add_argument("--u8", action="store_true", help="also write 8-bit frames")
+    ap.add_argument("--u8-only", action="store_true", help="write 8-bit frames only")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="method flags: 1 decay then add, 2 lazy (undecayed) snapshots")
     ap.add_argument("--cpu-sample-s", type=float, default=0.0,
                     help="seconds of the workload the CPU oracle is timed on (0: all of it)")
     ap.add_argument("--cpu-min-s", type=float, default=10.0,
@@ -105,6 +108,9 @@ def main() -> int:
     log(f"[bench] workload {args.workload}: {W}x{H}, {n} events, {nf} frames "
         f"(generated in {time.time() - t0:.1f} s)")
     prm = dict(evgen.DEFAULT_PARAMS)
+    prm["flags"] = args.flags
+    want_f32 = not args.u8_only
+    want_u8 = args.u8 or args.u8_only
 
     dev = torch.device("cuda", 0)
     x_d = torch.from_numpy(s.x.view(np.int16)).to(dev)
@@ -112,8 +118,8 @@ def main() -> int:
     t_d = torch.from_numpy(s.t).to(dev)
     p_d = torch.from_numpy(s.p).to(dev)
     tf_d = torch.from_numpy(tf).to(dev)
-    frames = torch.empty((nf, H, W), dtype=torch.float32, device=dev)
-    frames_u8 = torch.empty((nf, H, W), dtype=torch.uint8, device=dev) if args.u8 else None
+    frames = torch.empty((nf, H, W), dtype=torch.float32, device=dev) if want_f32 else None
+    frames_u8 = torch.empty((nf, H, W), dtype=torch.uint8, device=dev) if want_u8 else None
     st = esi.State(W, H, **prm)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
@@ -122,7 +128,7 @@ def main() -> int:
         assert rc == esi.ESI_OK, esi.esi_status_string(rc)
         rc = esi.esi_integrate_window(
             st.handle, x_d.data_ptr(), y_d.data_ptr(), t_d.data_ptr(), p_d.data_ptr(), n,
-            tf_d.data_ptr(), nf, frames.data_ptr(),
+            tf_d.data_ptr(), nf, frames.data_ptr() if frames is not None else None,
             frames_u8.data_ptr() if frames_u8 is not None else None, stream)
         assert rc == esi.ESI_OK, esi.esi_status_string(rc)
 
@@ -159,7 +165,7 @@ def main() -> int:
         log(f"[bench] copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
         del a, b
 
-    alg = algorithmic_bytes(n, npix, nf, args.u8)
+    alg = algorithmic_bytes(n, npix, nf, want_u8, want_f32)
     integ_avg_ms = integ_ms / calls
     roofline = {
         "kernel": "k_integrate (per-tile event loop + frames)",
@@ -168,7 +174,8 @@ def main() -> int:
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(alg / (integ_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "traffic": None if args.u8 else measured_traffic(args.workload, args.fps),
+        "traffic": (measured_traffic(args.workload, args.fps)
+                    if (want_f32 and not want_u8 and args.flags == 0) else None),
         "algorithmic_bytes": alg,
         "avg_launch_ms": round(integ_avg_ms, 4),
     }
@@ -183,20 +190,27 @@ def main() -> int:
     if not args.no_parity:
         import oracle
         sys.path.insert(0, os.path.join(ROOT, "tests"))
-        from esi_parity import REL
+        from esi_parity import REL, u8_codes
         sel = sorted(set([0, nf // 3, nf // 2, nf - 1]))
         h0 = time.time()
         o = oracle.State(W, H, oracle.Params(**prm))
         fo = o.integrate(s.x, s.y, s.t, s.p, t_frames=tf, frame_sel=sel)
         S, T, N, P = (a.cpu().numpy() for a in st.read_state())
-        fg = frames[sel].cpu().numpy()
         floor_f = prm["C"] / (prm["s_max"] - prm["s_min"])
         s_err = np.abs(S.astype(np.float64) - o.S) / np.maximum(np.abs(o.S), prm["C"])
-        f_err = np.abs(fg.astype(np.float64) - fo) / np.maximum(np.abs(fo), floor_f)
+        f_max = 0.0
+        if frames is not None:
+            fg = frames[sel].cpu().numpy()
+            f_max = float((np.abs(fg.astype(np.float64) - fo) / np.maximum(np.abs(fo), floor_f)).max())
+        u8_max = 0
+        if frames_u8 is not None:
+            ug = frames_u8[sel].cpu().numpy()
+            u8_max = int(np.abs(ug.astype(np.int32) - u8_codes(fo).astype(np.int32)).max())
         ok = (np.array_equal(N.view(np.uint32), o.N) and np.array_equal(P, o.P)
-              and np.array_equal(T, o.T) and s_err.max() <= REL and f_err.max() <= REL)
+              and np.array_equal(T, o.T) and s_err.max() <= REL and f_max <= REL
+              and u8_max <= 1)
         parity = {"ok": bool(ok), "max_rel_S": float(s_err.max()),
-                  "max_rel_frame": float(f_err.max()), "frames_checked": sel,
+                  "max_rel_frame": f_max, "max_u8_code_diff": u8_max, "frames_checked": sel,
                   "exact_N_P_T": bool(np.array_equal(N.view(np.uint32), o.N)
                                       and np.array_equal(P, o.P) and np.array_equal(T, o.T))}
         log(f"[bench] parity vs oracle: {parity} ({time.time() - h0:.1f} s)")
@@ -242,9 +256,12 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W}x{H}, {s.duration_us / 1e6:g} s, "
                                f"{n} events, {nf} frames at {args.fps:g} FPS"
-                               + (", +u8 frames" if args.u8 else ""),
+                               + (", 8-bit frames only" if args.u8_only
+                                  else ", +u8 frames" if args.u8 else "")
+                               + (f", flags {args.flags}" if args.flags else ""),
                    "events": n, "frames": nf, "width": W, "height": H,
-                   "params": prm, "frame_dtype": "f32"},
+                   "params": prm,
+                   "frame_dtype": "u8" if args.u8_only else ("f32+u8" if args.u8 else "f32")},
         "roofline": roofline,
         "roofline_path": roofline_path,
         "parity": parity,

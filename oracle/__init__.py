@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "libesi_oracle.so")
 
 DECAY_THEN_ADD = 1
 SNAPSHOT_LAZY = 2
+DECAY_EXP = 4
 
 
 def build(src: str = _SRC, out: str = _LIB) -> str:
@@ -48,6 +49,8 @@ def load(path: str = _LIB) -> ctypes.CDLL:
     i32, i64, f64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
     lib.esi_oracle_decay.argtypes = [f64, f64, f64]
     lib.esi_oracle_decay.restype = f64
+    lib.esi_oracle_decay_exp.argtypes = [f64, f64]
+    lib.esi_oracle_decay_exp.restype = f64
     lib.esi_oracle_init_state.argtypes = [i64, i64, P, P, P, P]
     lib.esi_oracle_init_state.restype = None
     lib.esi_oracle_snapshot.argtypes = [i64, P, P, i64, f64, f64, f64, f64, u32, P]
@@ -83,6 +86,12 @@ def decay(dt, k, b, lib=None):
     """Eq. (4), scalar."""
     lib = lib or load()
     return lib.esi_oracle_decay(float(dt), float(k), float(b))
+
+
+def decay_exp(dt, k, lib=None):
+    """The accumulator plugin's exponential decay exp(-k dt), scalar."""
+    lib = lib or load()
+    return lib.esi_oracle_decay_exp(float(dt), float(k))
 
 
 def u8(F, lib=None):

@@ -32,6 +32,9 @@
  *     default the state is decayed to t_f and clamped (the decay-to-query-time
  *     of Eq. (3)); flag LAZY maps S as stored, as Alg. 2's final loop does.
  *   - flag DECAY_THEN_ADD swaps the first two steps (decay, then add).
+ *   - flag DECAY_EXP replaces Eq. (4) by the plain exponential decay
+ *     d(dt) = exp(-k dt) of the accumulator plugin the paper compares against
+ *     (Sec. II, and the runtime discussion of Sec. IV); b is then unused.
  *
  * Parity pins for every function here live in tests/test_oracle_pins.py.
  */
@@ -42,6 +45,7 @@
 
 #define ORACLE_DECAY_THEN_ADD 1u
 #define ORACLE_SNAPSHOT_LAZY 2u
+#define ORACLE_DECAY_EXP 4u
 
 /* Eq. (4): d(t) = max{(1 - k t)^b, 0}, read as max(1 - k t, 0)^b. */
 double esi_oracle_decay(double dt, double k, double b)
@@ -50,6 +54,20 @@ double esi_oracle_decay(double dt, double k, double b)
     if (u <= 0.0)
         return 0.0;
     return pow(u, b);
+}
+
+/* The exponential decay of the accumulator plugin: d(t) = exp(-k t). */
+double esi_oracle_decay_exp(double dt, double k)
+{
+    return exp(-k * dt);
+}
+
+/* The decay a call uses: Eq. (4), or the exponential one under DECAY_EXP. */
+static double decay_of(double dt, double k, double b, uint32_t flags)
+{
+    if (flags & ORACLE_DECAY_EXP)
+        return esi_oracle_decay_exp(dt, k);
+    return esi_oracle_decay(dt, k, b);
 }
 
 /* Eq. (13). */
@@ -86,7 +104,7 @@ static double frame_value(double S, int64_t T, int64_t t_f, double k, double b,
         int64_t dt = t_f - T;
         if (dt < 0)
             dt = 0;
-        v = clamp_s(S * esi_oracle_decay((double)dt, k, b), s_min, s_max);
+        v = clamp_s(S * decay_of((double)dt, k, b, flags), s_min, s_max);
     }
     return (v - s_min) / (s_max - s_min);
 }
@@ -164,7 +182,7 @@ void esi_oracle_integrate(int32_t W, int32_t H, double C, double k, double b,
         int64_t dt = t[i] - T[q];
         if (dt < 0)
             dt = 0;
-        const double d = esi_oracle_decay((double)dt, k, b);
+        const double d = decay_of((double)dt, k, b, flags);
         if (flags & ORACLE_DECAY_THEN_ADD)
             S[q] = S[q] * d + pol * C;
         else

@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import itertools
 import json
+import math
 import os
 
 import numpy as np
@@ -422,6 +423,90 @@ def pin_stream_origin(lib):
     assert st.T[0] == 10_000_000
     st.integrate([0], [0], [10_250_000], [1], want_frames=False)
     assert st.S[0] == 0.125
+
+
+def pin_exp_decay_values(lib):
+    """The accumulator plugin's decay exp(-k t): 1 at 0, e^-1 at 1/k, e^-2 at
+    2/k, a semigroup (d(a + b) = d(a) d(b)), 1 for k = 0, and no cutoff
+    (still positive at 40/k, where Eq. (4) is 0)."""
+    k = 2e-6
+    assert oracle.decay_exp(0.0, k, lib=lib) == 1.0
+    for m in (1, 2, 5):
+        want = math.exp(-m)
+        assert abs(oracle.decay_exp(m / k, k, lib=lib) - want) <= 1e-15 * want
+    for a, b in [(1234.0, 98765.0), (5e5, 2.5e5), (0.0, 7e5)]:
+        lhs = oracle.decay_exp(a + b, k, lib=lib)
+        rhs = oracle.decay_exp(a, k, lib=lib) * oracle.decay_exp(b, k, lib=lib)
+        assert abs(lhs - rhs) <= 4e-16 * lhs
+    assert oracle.decay_exp(1e9, 0.0, lib=lib) == 1.0
+    assert oracle.decay_exp(40 / k, k, lib=lib) > 0.0
+
+
+def pin_exp_constant_rate_geometric(lib):
+    """Exponential decay, one pixel, n events of +1 every D us: the geometric
+    sums of the constant-rate pin with q = exp(-k D)."""
+    for (k, D, n, C) in [(2e-6, 10_000, 300, 0.2), (1e-4, 3_000, 50, 0.25)]:
+        q = math.exp(-k * D)
+        t = np.arange(1, n + 1, dtype=np.int64) * D
+        ones = np.ones(n, np.int8)
+        zeros = np.zeros(n, np.uint16)
+        for flags, geo in [(oracle.DECAY_EXP, C * q * (1 - q ** n) / (1 - q)),
+                           (oracle.DECAY_EXP | oracle.DECAY_THEN_ADD, C * (1 - q ** n) / (1 - q))]:
+            st = oracle.State(1, 1, oracle.Params(C=C, k_per_us=k, b=2.0, s_min=-1e30,
+                                                  s_max=1e30, flags=flags), lib=lib)
+            st.integrate(zeros, zeros, t, ones, want_frames=False)
+            assert abs(st.S[0] - geo) <= 1e-12 * abs(geo), (k, flags, st.S[0], geo)
+
+
+def pin_exp_telescoped_sum(lib):
+    """With exponential decay the product in Eq. (5) telescopes: without a
+    clamp, add-then-decay gives S_n = C sum_i p_i exp(-k (t_n - t_{i-1}))
+    (t_0 = the initial T) and decay-then-add S_n = C sum_i p_i
+    exp(-k (t_n - t_i)).  Random short runs, one per pixel, gaps including
+    0; b is ignored under the flag (checked with two values)."""
+    rng = np.random.default_rng(2024)
+    k, C, W = 1e-5, 0.2, 40
+    n_per = rng.integers(1, 9, W)
+    xs, ts, ps = [], [], []
+    runs = []
+    for q in range(W):
+        gaps = rng.choice([0, 1, 50, 20_000, 100_000, 400_000], n_per[q])
+        tq = np.cumsum(gaps)
+        pq = rng.choice([-1, 1], n_per[q])
+        runs.append((tq, pq))
+        xs += [q] * len(tq)
+        ts += list(tq)
+        ps += list(pq)
+    order = np.argsort(np.array(ts), kind="stable")
+    x = np.array(xs, np.uint16)[order]
+    t = np.array(ts, np.int64)[order]
+    p = np.array(ps, np.int8)[order]
+    for dta in (False, True):
+        for b in (2.0, 0.5):
+            flags = oracle.DECAY_EXP | (oracle.DECAY_THEN_ADD if dta else 0)
+            st = oracle.State(W, 1, oracle.Params(C=C, k_per_us=k, b=b, s_min=-1e30,
+                                                  s_max=1e30, flags=flags), lib=lib)
+            st.integrate(x, np.zeros_like(x), t, p, want_frames=False)
+            for q, (tq, pq) in enumerate(runs):
+                tn = float(tq[-1])
+                prev = np.concatenate([[0.0], tq[:-1].astype(np.float64)])
+                ref = tq.astype(np.float64) if dta else prev
+                want = C * float(np.sum(pq * np.exp(-k * (tn - ref))))
+                assert abs(st.S[q] - want) <= 1e-12 * max(abs(want), C), (q, dta, st.S[q], want)
+
+
+def pin_exp_event_free_window(lib):
+    """Exponential decay: a frame at t_f with no event after T shows
+    S exp(-k (t_f - T)), mapped by Eq. (14)."""
+    k = 3e-6
+    prm = oracle.Params(C=0.5, k_per_us=k, b=1.0, s_min=-1.0, s_max=1.0,
+                        flags=oracle.DECAY_EXP)
+    st = oracle.State(1, 1, prm, lib=lib)
+    tf = [0, 100_000, 333_333, 10**6, 10**7]
+    frames = st.integrate([0], [0], [0], [1], t_frames=tf)
+    for j, tj in enumerate(tf):
+        want = (0.5 * math.exp(-k * tj) + 1.0) / 2.0
+        assert abs(frames[j, 0, 0] - want) <= 1e-15, (tj, frames[j, 0, 0], want)
 
 
 PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -39,7 +39,7 @@ MUTANTS = [
     ("polarity_count", "P[q] += pol;", "P[q] += 1;"),
     ("negative_dt_kept", "        if (dt < 0)\n            dt = 0;\n        const double d",
      "        const double d"),
-    ("snapshot_not_decayed", "v = clamp_s(S * esi_oracle_decay((double)dt, k, b), s_min, s_max);",
+    ("snapshot_not_decayed", "v = clamp_s(S * decay_of((double)dt, k, b, flags), s_min, s_max);",
      "v = clamp_s(S, s_min, s_max);"),
     ("snapshot_decay_from_zero", "int64_t dt = t_f - T;", "int64_t dt = t_f;"),
     ("out_of_range_x_only", "if (x[i] >= W || y[i] >= H) {", "if (x[i] >= W) {"),
@@ -48,6 +48,10 @@ MUTANTS = [
     ("u8_round_down", "volatile float a = m + 0.5f;", "volatile float a = m;"),
     ("decay_then_add_order", "S[q] = S[q] * d + pol * C;", "S[q] = (S[q] + pol * C) * d;"),
     ("lazy_ignored", "if (!(flags & ORACLE_SNAPSHOT_LAZY)) {", "if (1) {"),
+    ("exp_sign", "return exp(-k * dt);", "return exp(k * dt);"),
+    ("exp_k_dropped", "return exp(-k * dt);", "return exp(-dt);"),
+    ("exp_first_order", "return exp(-k * dt);", "return 1.0 - k * dt;"),
+    ("exp_flag_ignored", "    if (flags & ORACLE_DECAY_EXP)\n        return esi_oracle_decay_exp(dt, k);\n", ""),
 ]
 
 

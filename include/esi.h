@@ -75,6 +75,11 @@ enum {
     ESI_DECAY_THEN_ADD = 1u << 0,  /* decay, then add */
     ESI_SNAPSHOT_DECAYED = 0,      /* frame shows clamp(S d(t_f - T)) (default) */
     ESI_SNAPSHOT_LAZY = 1u << 1,   /* frame shows S as stored (Alg. 2's map loop) */
+    ESI_DECAY_EXP = 1u << 2,       /* d(dt) = exp(-k dt) in place of Eq. (4), for every event
+                                      and snapshot (b unused): the exponential decay of the
+                                      event-accumulator plugin the paper compares ESI with
+                                      (Sec. II; Sec. IV attributes the plugin's lower runtime
+                                      to this cheaper function) */
 };
 
 /* diag.flags */

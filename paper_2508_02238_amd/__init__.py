@@ -26,6 +26,7 @@ ESI_ADD_THEN_DECAY = 0
 ESI_DECAY_THEN_ADD = 1
 ESI_SNAPSHOT_DECAYED = 0
 ESI_SNAPSHOT_LAZY = 2
+ESI_DECAY_EXP = 4
 
 ESI_DIAG_UNSORTED = 1
 ESI_DIAG_FRAMES_UNSORTED = 2

@@ -53,7 +53,7 @@ bool params_ok(const esi_params* p)
     return p && std::isfinite(p->C) && p->C > 0.0 && std::isfinite(p->k_per_us) &&
            p->k_per_us >= 0.0 && std::isfinite(p->b) && p->b > 0.0 && std::isfinite(p->s_min) &&
            std::isfinite(p->s_max) && p->s_min < p->s_max &&
-           (p->flags & ~(uint32_t)(ESI_DECAY_THEN_ADD | ESI_SNAPSHOT_LAZY)) == 0;
+           (p->flags & ~(uint32_t)(ESI_DECAY_THEN_ADD | ESI_SNAPSHOT_LAZY | ESI_DECAY_EXP)) == 0;
 }
 
 MethodParams method_params(const esi_params& p)
@@ -73,6 +73,7 @@ MethodParams method_params(const esi_params& p)
     mp.need_clamp = (p.s_min > 0.0 || p.s_max < 0.0) ? 1 : 0;
     mp.decay_then_add = (p.flags & ESI_DECAY_THEN_ADD) ? 1 : 0;
     mp.lazy = (p.flags & ESI_SNAPSHOT_LAZY) ? 1 : 0;
+    mp.exp_decay = (p.flags & ESI_DECAY_EXP) ? 1 : 0;
     return mp;
 }
 

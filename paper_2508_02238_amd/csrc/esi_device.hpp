@@ -25,12 +25,15 @@ struct MethodParams {
     double sv_min, sv_max;                    // s_min * inv_range, s_max * inv_range
     int decay_then_add;
     int lazy;
+    int exp_decay;   // d = exp(-k dt) instead of Eq. (4)
     int need_clamp;  // a decayed state can leave [s_min, s_max]
 };
 
-// How d = max(1 - k dt, 0)^b is evaluated: b = 1 and b = 2 exactly by
-// multiplication, any other b by pow().
-enum DecayKind { kDecayB1 = 1, kDecayB2 = 2, kDecayPow = 0 };
+// How the decay is evaluated: Eq. (4), d = max(1 - k dt, 0)^b, with b = 1 and
+// b = 2 exactly by multiplication and any other b by pow(); or the
+// exponential decay exp(-k dt) of the accumulator plugin the paper compares
+// against (Sec. II; Sec. IV ties its lower runtime to that cheaper function).
+enum DecayKind { kDecayB1 = 1, kDecayB2 = 2, kDecayPow = 0, kDecayExp = 3 };
 
 __device__ __noinline__ double decay_pow(double u, double b) { return pow(u, b); }
 
@@ -45,10 +48,24 @@ __device__ __forceinline__ double power_b(double u, double b)
     return decay_pow(u, b);
 }
 
-// Eq. (4) as a truncated power: d(dt) = max(1 - k dt, 0)^b, dt >= 0 integer us.
+// The decay from its base x = 1 - k dt (dt >= 0, so x <= 1 up to rounding):
+// Eq. (4) clamps x to [0, 1] and raises it to b; the exponential decay is
+// exp(x - 1).
+template <int BK>
+__device__ __forceinline__ double decay_from_base(double x, double b)
+{
+    if (BK == kDecayExp)
+        return exp(fmin(x, 1.0) - 1.0);
+    return power_b<BK>(fmin(fmax(x, 0.0), 1.0), b);
+}
+
+// Eq. (4) as a truncated power: d(dt) = max(1 - k dt, 0)^b, dt >= 0 integer
+// us; or exp(-k dt).
 template <int BK>
 __device__ __forceinline__ double decay(const MethodParams& mp, int64_t dt)
 {
+    if (BK == kDecayExp)
+        return exp(-mp.k * (double)dt);
     const double u = __fma_rn(-mp.k, (double)dt, 1.0);
     return (u > 0.0) ? power_b<BK>(u, mp.b) : 0.0;
 }

@@ -164,6 +164,11 @@ __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& 
         double F;
         if (LAZY) {
             F = px.Sv[i] + mp.f_off;
+        } else if (BK == kDecayExp) {
+            double w = px.Sv[i] * decay_from_base<BK>(px.Av[i] - kt, mp.b);
+            if (CLAMP)
+                w = fmin(fmax(w, mp.sv_min), mp.sv_max);
+            F = w + mp.f_off;
         } else {
             const double u = fmin(fmax(px.Av[i] - kt, 0.0), 1.0);
             if (BK == kDecayB2 && !CLAMP) {
@@ -595,8 +600,7 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
                             ++w;
                         }
                         jc_prev = jc;
-                        const double u = fmin(fmax(A - kt, 0.0), 1.0);
-                        const double d = power_b<BK>(u, mp.b);
+                        const double d = decay_from_base<BK>(A - kt, mp.b);
                         // +C or -C: the polarity flips the sign bit of C
                         const double s = __hiloint2double((int)(c_hi + (neg << 31)), (int)c_lo);
                         if constexpr (decltype(decay_then_add)::value)
@@ -715,7 +719,12 @@ __global__ __launch_bounds__(kBlock) void k_reset(StateDev st, int64_t t0, DiagD
     }
 }
 
-int decay_kind(double b) { return b == 1.0 ? kDecayB1 : (b == 2.0 ? kDecayB2 : kDecayPow); }
+int decay_kind(const MethodParams& mp)
+{
+    if (mp.exp_decay)
+        return kDecayExp;
+    return mp.b == 1.0 ? kDecayB1 : (mp.b == 2.0 ? kDecayB2 : kDecayPow);
+}
 
 template <int PPT, int NB, int BK>
 hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Schedule& sc,
@@ -737,13 +746,16 @@ hipError_t launch_integrate_p(const EventsDev& ev, const StateDev& st, const Sch
                               const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
                               DiagDev* diag, hipStream_t stream)
 {
-    switch (decay_kind(mp.b)) {
+    switch (decay_kind(mp)) {
     case kDecayB1:
         return launch_integrate_t<PPT, NB, kDecayB1>(ev, st, sc, cs, mp, t_frames, nf, frames,
                                                  frames_u8, diag, stream);
     case kDecayB2:
         return launch_integrate_t<PPT, NB, kDecayB2>(ev, st, sc, cs, mp, t_frames, nf, frames,
                                                  frames_u8, diag, stream);
+    case kDecayExp:
+        return launch_integrate_t<PPT, NB, kDecayExp>(ev, st, sc, cs, mp, t_frames, nf, frames,
+                                                  frames_u8, diag, stream);
     default:
         return launch_integrate_t<PPT, NB, kDecayPow>(ev, st, sc, cs, mp, t_frames, nf, frames,
                                                   frames_u8, diag, stream);
@@ -780,13 +792,17 @@ hipError_t launch_snapshot(const StateDev& st, const MethodParams& mp, int64_t t
                            uint8_t* u8, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((st.npix + kBlock - 1) / kBlock);
-    switch (decay_kind(mp.b)) {
+    switch (decay_kind(mp)) {
     case kDecayB1:
         hipLaunchKernelGGL(k_snapshot<kDecayB1>, dim3(blocks), dim3(kBlock), 0, stream, st, mp,
                            t_f, frame, u8);
         break;
     case kDecayB2:
         hipLaunchKernelGGL(k_snapshot<kDecayB2>, dim3(blocks), dim3(kBlock), 0, stream, st, mp,
+                           t_f, frame, u8);
+        break;
+    case kDecayExp:
+        hipLaunchKernelGGL(k_snapshot<kDecayExp>, dim3(blocks), dim3(kBlock), 0, stream, st, mp,
                            t_f, frame, u8);
         break;
     default:

@@ -48,6 +48,12 @@ PARAM_SWEEP = [
     dict(C=0.2, k_per_us=2e-6, b=1.0, s_min=-1e30, s_max=1e30, flags=1),
     dict(C=0.2, k_per_us=5e-6, b=3.0, s_min=-0.5, s_max=0.5, flags=2),
     dict(C=0.3, k_per_us=3e-6, b=2.0, s_min=-0.3, s_max=0.7, flags=3),
+    # exponential decay (flag 4): alone, with decay-then-add, lazy, and with
+    # clamp bounds that exclude 0
+    dict(C=0.2, k_per_us=2e-6, b=2.0, s_min=-1.0, s_max=1.0, flags=4),
+    dict(C=0.25, k_per_us=1e-4, b=0.7, s_min=-0.4, s_max=0.6, flags=5),
+    dict(C=0.2, k_per_us=5e-6, b=3.0, s_min=-0.5, s_max=0.5, flags=6),
+    dict(C=0.2, k_per_us=3e-6, b=1.0, s_min=0.1, s_max=0.9, flags=4),
 ]
 
 
@@ -276,6 +282,20 @@ def test_large_sensors(esi, W, H, prm):
     assert_state(stg, o, prm["C"], f"{W}x{H}")
     assert_frames(fg, fo, prm, f"{W}x{H}")
     assert diag["accepted"] == s.n - o.dropped
+
+
+@pytest.mark.parametrize("flags", [4, 5])
+def test_exp_decay_workload(esi, flags):
+    """The exponential decay variant on the 640x480 workload in the
+    benchmark's launch configuration: state and sampled frames."""
+    s = evgen.preset("c2")
+    tf = s.frame_times(100)
+    prm = dict(DEFAULT, flags=flags)
+    sel = [0, 1, 500, 999]
+    fg, _, stg, diag = gpu_run(esi, s, prm, t_frames=tf, frame_sel=sel)
+    fo, o = oracle_run(s, prm, t_frames=tf, frame_sel=sel)
+    assert_state(stg, o, prm["C"], f"exp {flags}")
+    assert_frames(fg, fo, prm, f"exp {flags}")
 
 
 def test_clamp_range_without_zero(esi):

@@ -30,6 +30,11 @@
 // so the base of Eq. (4) is u = A - kt = 1 - k (t_f - T).  A segment's frames
 // span at most kMaxSegmentDecay decay lengths, which bounds the rounding of u
 // by a few ulp of that span (a longer gap gives a one-frame segment, kt = 0).
+// Under the exponential decay the factors separate instead:
+// exp(-k (t_f - T)) = exp(k (T - t_b)) exp(-k (t_f - t_b)), so a visible
+// state keeps G = exp(k (T - t_b)), a frame E = exp(-k (t_f - t_b)), and the
+// frame's decay is min(G E, 1) (the 1 for a T after t_f); a segment then spans
+// at most kMaxSegmentExp decay lengths, so that G and E stay normal numbers.
 //
 // Chunk boundaries come from a few scalar loads (first and last record of
 // the window, first frame time after it) prefetched one chunk ahead; only a
@@ -50,6 +55,7 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr int kFrameGroup = 112;                    // frames per segment, at most
 constexpr int kSearchTop = 64;                      // largest power of two <= kFrameGroup
 constexpr double kMaxSegmentDecay = 1073741824.0;   // 2^30
+constexpr double kMaxSegmentExp = 600.0;            // e^600 and e^-600 are normal doubles
 constexpr int kNever = 0x7FFFFFFF;                  // "no further change"
 constexpr uint64_t kLpxMask = (uint64_t)0x7FFF << 48;
 
@@ -99,6 +105,7 @@ struct Pixels {
     uint32_t N[PPT];
     int32_t P[PPT];
     // the state the frames see: Sv = S / (s_max - s_min) and Av = 1 + k (T - t_b)
+    // (exponential decay: Av = exp(k (T - t_b)))
     double Sv[PPT], Av[PPT];
     // change list of the segment: byte offsets of the next change's entry in
     // chg_S / chg_A (8-byte entries) and of the frame index after it in chg_j
@@ -165,7 +172,8 @@ __device__ __forceinline__ void frame_step(const MethodParams& mp, Pixels<PPT>& 
         if (LAZY) {
             F = px.Sv[i] + mp.f_off;
         } else if (BK == kDecayExp) {
-            double w = px.Sv[i] * decay_from_base<BK>(px.Av[i] - kt, mp.b);
+            // kt holds the frame's factor E here and Av the state's G
+            double w = px.Sv[i] * fmin(px.Av[i] * kt, 1.0);
             if (CLAMP)
                 w = fmin(fmax(w, mp.sv_min), mp.sv_max);
             F = w + mp.f_off;
@@ -212,7 +220,7 @@ __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>&
 }
 
 // Phase B over the nfw frames of one segment; ktv0 / ktv1 hold k (t_f - t_b)
-// of frames lane and 64 + lane.
+// of frames lane and 64 + lane (exponential decay: exp(-k (t_f - t_b))).
 template <int PPT, int NB, int BK, bool LAZY, bool CLAMP, int OUT>
 __device__ __forceinline__ void walk_segment(const MethodParams& mp, Pixels<PPT>& px, int nfw,
                                              double ktv0, double ktv1, const double* chg_S,
@@ -384,7 +392,8 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
         // ---- chunk and segment bounds (uniform) ----
         const int jmax0 = min(j + kFrameGroup, nf);
         int jmax = jmax0;
-        if (jmax > j + 1 && mp.k * (double)(c.tf_hi - c.tb) > kMaxSegmentDecay)
+        if (jmax > j + 1 &&
+            mp.k * (double)(c.tf_hi - c.tb) > (BK == kDecayExp ? kMaxSegmentExp : kMaxSegmentDecay))
             jmax = j + 1;
         const int64_t tf_lim = (jmax < nf) ? (jmax == jmax0 ? c.tf_hi : c.tb) : INT64_MAX;
         uint32_t cn;
@@ -434,7 +443,8 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             px.Sv[i] = px.S[i] * mp.inv_range;
-            px.Av[i] = __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
+            px.Av[i] = (BK == kDecayExp) ? exp(mp.k * (double)(px.T[i] - tb))
+                                         : __fma_rn(mp.k, (double)(px.T[i] - tb), 1.0);
         }
         uint32_t rank[STEPS];
         if (cn > 0) {
@@ -455,8 +465,12 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
         __syncthreads();
         // decay bases k (t_f - t_b) of the segment's frames, one per lane:
         // frames lane and 64 + lane
-        const double ktv0 = mp.k * (double)(tfl[lane] - tb);
-        const double ktv1 = mp.k * (double)(tfl[min(kWave + lane, kFrameGroup - 1)] - tb);
+        double ktv0 = mp.k * (double)(tfl[lane] - tb);
+        double ktv1 = mp.k * (double)(tfl[min(kWave + lane, kFrameGroup - 1)] - tb);
+        if (BK == kDecayExp) {  // the frames' factors exp(-k (t_f - t_b))
+            ktv0 = exp(-ktv0);
+            ktv1 = exp(-ktv1);
+        }
         int j_end = jmax;
         if (search)
             j_end = j + frames_before(tfl, jmax - j, c.t_after);
@@ -562,7 +576,8 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
             // The change list keeps, per segment frame jc that first includes
             // some event, the state after the last such event, written once
             // the next event belongs to a later frame (or the run ends); its
-            // decay base is A + k (t_first - t_b).  Entries go over the
+            // decay base is A + k (t_first - t_b) (exponential decay: the
+            // factor exp of that minus 1).  Entries go over the
             // pixel's own slots of `sorted`/`ktvs`, behind the read position
             // (an entry written at event e lands at or before e - 1, while the
             // loop has already read e + 1).  Events after the segment
@@ -595,7 +610,7 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
                         if (jc != jc_prev && jc_prev < nfw) {
                             // the group of event e - 1 is complete
                             chg_S[w] = S * mp.inv_range;
-                            chg_A[w] = A + dA;
+                            chg_A[w] = (BK == kDecayExp) ? exp(A + dA - 1.0) : A + dA;
                             chg_j[w + l] = (uint16_t)jc_prev;
                             ++w;
                         }
@@ -619,7 +634,7 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
                     const uint64_t rl = sorted[end - 1];  // the run's last event
                     if (jc_prev < nfw) {
                         chg_S[w] = S * mp.inv_range;
-                        chg_A[w] = A + dA;
+                        chg_A[w] = (BK == kDecayExp) ? exp(A + dA - 1.0) : A + dA;
                         chg_j[w + l] = (uint16_t)jc_prev;
                         ++w;
                     }

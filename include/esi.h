@@ -191,6 +191,38 @@ esi_status esi_profile_enable(esi_state *st, int enable);
 esi_status esi_profile_read(esi_state *st, uint32_t *calls, double *bucket_ms,
                             double *integrate_ms);
 
+/* ---- many streams per launch -------------------------------------------
+ * The same integration (Alg. 2 per pixel, frames by Eq. (14)) for many
+ * independent states at once: each launch of the bucketing and integration
+ * kernels covers the work of every stream (per stream: its bucketing ranges,
+ * table scan and tiles, laid out one after the other), instead of one set
+ * of launches per stream.  Results are those of one esi_integrate_window call
+ * per item, bit for bit.
+ *
+ * A batch object owns the staging of the per-stream descriptors (pinned host
+ * memory and a device copy, sized for max_items, 1..4096) on the current
+ * device. */
+typedef struct esi_batch esi_batch;
+esi_status esi_batch_create(int32_t max_items, esi_batch **out);
+/* Synchronises the batch's device (earlier calls may still read it). */
+esi_status esi_batch_destroy(esi_batch *batch);
+
+/* Item i integrates events[i] into states[i] and writes n_frames[i] frames
+ * at t_frames[i] into frames[i] / frames_u8[i], with the rules of
+ * esi_integrate_window for each item (all in device memory, all on the
+ * batch's device).  states: n_items distinct states (host array of
+ * pointers); events: host array of n_items descriptors.  t_frames, n_frames,
+ * frames, frames_u8: host arrays of n_items entries, or NULL for "no frames"
+ * / "no such output" for every item.  1 <= n_items <= max_items.  Argument
+ * errors return ESI_ERR_INVALID_ARG before anything is enqueued; a poisoned
+ * state returns ESI_ERR_POISONED; a HIP failure poisons every state of the
+ * call.  The call may wait for the previous call's descriptor copy (host
+ * side) and for the stream when a state's scratch must grow. */
+esi_status esi_integrate_batch(esi_batch *batch, int32_t n_items, esi_state *const *states,
+                               const esi_events *events, const int64_t *const *t_frames,
+                               const int32_t *n_frames, float *const *frames,
+                               uint8_t *const *frames_u8, hipStream_t stream);
+
 /* Static text for a status code. */
 const char *esi_status_string(esi_status s);
 

@@ -73,6 +73,12 @@ _SIGNATURES = [
     ("esi_profile_read", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint32),
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
+    ("esi_batch_create", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP)]),
+    ("esi_batch_destroy", ctypes.c_int, [_VP]),
+    ("esi_integrate_batch", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP),
+                                           ctypes.POINTER(esi_events), ctypes.POINTER(_VP),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_VP),
+                                           ctypes.POINTER(_VP), _VP]),
     ("esi_status_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
@@ -133,6 +139,29 @@ def esi_integrate_window(st, x_ptr, y_ptr, t_ptr, p_ptr, n, t_frames_ptr, n_fram
     return lib.esi_integrate_window(_VP(st), ctypes.byref(ev), _VP(t_frames_ptr),
                                     int(n_frames), _VP(frames_ptr), _VP(frames_u8_ptr),
                                     _VP(stream))
+
+
+def esi_batch_create(max_items: int):
+    out = _VP()
+    rc = lib.esi_batch_create(int(max_items), ctypes.byref(out))
+    return rc, out.value
+
+
+def esi_batch_destroy(batch) -> int:
+    return lib.esi_batch_destroy(_VP(batch))
+
+
+def esi_integrate_batch(batch, states, events, t_frames=None, n_frames=None, frames=None,
+                        frames_u8=None, stream: int = 0) -> int:
+    """states: state handles; events: (x, y, t, p, n) pointer tuples; the
+    other per-item lists hold pointers / counts, or are None for all items."""
+    m = len(states)
+    st = (_VP * m)(*[_VP(s) for s in states])
+    ev = (esi_events * m)(*[esi_events(*e[:4], int(e[4])) for e in events])
+    arr = lambda v, ty: None if v is None else (ty * m)(*v)
+    return lib.esi_integrate_batch(_VP(batch), m, st, ev, arr(t_frames, _VP),
+                                   arr(n_frames, ctypes.c_int32), arr(frames, _VP),
+                                   arr(frames_u8, _VP), _VP(stream))
 
 
 def esi_snapshot_frame(st, t_frame_us: int, frame_ptr, u8_ptr, stream: int = 0) -> int:
@@ -307,3 +336,63 @@ class State:
         rc, d = esi_get_diagnostics(self.handle)
         _check(rc, "esi_get_diagnostics")
         return d
+
+
+class Batch:
+    """Integrate many States with one set of kernel launches per call."""
+
+    def __init__(self, max_items: int):
+        import torch
+        self._torch = torch
+        rc, h = esi_batch_create(int(max_items))
+        _check(rc, "esi_batch_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            esi_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def integrate(self, states, events, t_frames=None, want_frames: bool = True,
+                  want_u8: bool = False):
+        """states: list of State; events: list of (x, y, t, p) per state;
+        t_frames: list of frame-time arrays (or None entries), or None.
+        Returns the list of (frames, frames_u8) per state."""
+        torch = self._torch
+        m = len(states)
+        keep, evp, tfp, nfs, frp, u8p, outs = [], [], [], [], [], [], []
+        ptr = lambda a: a.data_ptr() if (a is not None and a.numel()) else None
+        for i, s in enumerate(states):
+            dev = s.device
+            x = State._dev(events[i][0], torch.uint16, torch, dev)
+            y = State._dev(events[i][1], torch.uint16, torch, dev)
+            t = State._dev(events[i][2], torch.int64, torch, dev)
+            p = State._dev(events[i][3], torch.int8, torch, dev)
+            n = x.numel()
+            tf = None
+            if t_frames is not None and t_frames[i] is not None and len(t_frames[i]):
+                tf = State._dev(t_frames[i], torch.int64, torch, dev)
+            nf = tf.numel() if tf is not None else 0
+            fr = (torch.empty((nf, s.height, s.width), dtype=torch.float32, device=dev)
+                  if nf and want_frames else None)
+            u8 = (torch.empty((nf, s.height, s.width), dtype=torch.uint8, device=dev)
+                  if nf and want_u8 else None)
+            keep += [x, y, t, p, tf]
+            evp.append((ptr(x), ptr(y), ptr(t), ptr(p), n))
+            tfp.append(ptr(tf) if nf else None)
+            nfs.append(nf)
+            frp.append(ptr(fr) if nf else None)
+            u8p.append(ptr(u8) if nf else None)
+            outs.append((fr, u8))
+        stream = torch.cuda.current_stream(states[0].device).cuda_stream
+        rc = esi_integrate_batch(self.handle, [s.handle for s in states], evp, tfp, nfs,
+                                 frp, u8p, stream)
+        _check(rc, "esi_integrate_batch")
+        self._keep = keep  # alive until the stream has consumed them
+        return outs

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "esi.h"
 #include "esi_internal.hpp"
@@ -35,11 +36,23 @@ struct esi_state {
     hipEvent_t* prof_ev = nullptr;  // [kProfMax][3]
 };
 
+// Descriptor staging of batched calls: pinned host copy and device copy.
+struct esi_batch {
+    int32_t max_items = 0;
+    int device = 0;
+    size_t bytes = 0;
+    void* host = nullptr;
+    void* dev = nullptr;
+    hipEvent_t copied = nullptr;  // recorded after the last staging copy
+    bool pending = false;
+};
+
 namespace {
 
 constexpr uint64_t kMagic = 0x3130495345ull;  // "ESI01"
 constexpr uint32_t kProfMax = 1024;
 constexpr int64_t kMaxPixels = (int64_t)kMaxTiles * 256 * 8;  // 4096000
+constexpr int32_t kMaxBatch = 4096;  // streams per batched call
 
 struct SerialHeader {
     uint64_t magic;
@@ -120,6 +133,43 @@ esi_status hip_fail(esi_state* st)
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// The scratch of one call with n > 0 events under schedule sc: table |
+// segment sums | tile totals | total | records, grown on demand (after the
+// stream has finished with the old one).
+esi_status call_scratch(esi_state* st, const Schedule& sc, int64_t n, hipStream_t stream,
+                        CallScratch& cs)
+{
+    const int64_t M = (int64_t)sc.ntiles * sc.nunits;
+    const int64_t nseg = (int64_t)scan_segments(sc.nunits);
+    const size_t o_bs = align_up(4 * (size_t)M, 256);
+    const size_t o_tt = o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
+    const size_t o_tot = o_tt + align_up(4 * (size_t)sc.ntiles, 256);
+    const size_t o_rec = o_tot + 256;
+    const size_t need = o_rec + 8 * (size_t)n;
+    if (need > st->scratch_bytes) {
+        // the old scratch may still be read by work queued on this stream
+        if (hipStreamSynchronize(stream) != hipSuccess)
+            return hip_fail(st);
+        if (st->scratch)
+            (void)hipFree(st->scratch);
+        st->scratch = nullptr;
+        st->scratch_bytes = 0;
+        const size_t bytes = need + need / 4;
+        if (hipMalloc(&st->scratch, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return ESI_ERR_OUT_OF_MEMORY;
+        }
+        st->scratch_bytes = bytes;
+    }
+    char* base = (char*)st->scratch;
+    cs.table = (uint32_t*)base;
+    cs.blocksum = (uint32_t*)(base + o_bs);
+    cs.tile_tot = (uint32_t*)(base + o_tt);
+    cs.total = (uint32_t*)(base + o_tot);
+    cs.records = (uint64_t*)(base + o_rec);
+    return ESI_OK;
+}
 
 }  // namespace
 
@@ -297,34 +347,9 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
     EventsDev evd{ev->x, ev->y, ev->t, ev->p, n};
     CallScratch cs{};
     if (n > 0) {
-        const int64_t M = (int64_t)sc.ntiles * sc.nunits;
-        const int64_t nseg = (int64_t)scan_segments(sc.nunits);
-        const size_t o_bs = align_up(4 * (size_t)M, 256);
-        const size_t o_tt = o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
-        const size_t o_tot = o_tt + align_up(4 * (size_t)sc.ntiles, 256);
-        const size_t o_rec = o_tot + 256;
-        const size_t need = o_rec + 8 * (size_t)n;
-        if (need > st->scratch_bytes) {
-            // the old scratch may still be read by work queued on this stream
-            if (hipStreamSynchronize(stream) != hipSuccess)
-                return hip_fail(st);
-            if (st->scratch)
-                (void)hipFree(st->scratch);
-            st->scratch = nullptr;
-            st->scratch_bytes = 0;
-            const size_t bytes = need + need / 4;
-            if (hipMalloc(&st->scratch, bytes) != hipSuccess) {
-                (void)hipGetLastError();
-                return ESI_ERR_OUT_OF_MEMORY;
-            }
-            st->scratch_bytes = bytes;
-        }
-        char* base = (char*)st->scratch;
-        cs.table = (uint32_t*)base;
-        cs.blocksum = (uint32_t*)(base + o_bs);
-        cs.tile_tot = (uint32_t*)(base + o_tt);
-        cs.total = (uint32_t*)(base + o_tot);
-        cs.records = (uint64_t*)(base + o_rec);
+        const esi_status rc = call_scratch(st, sc, n, stream, cs);
+        if (rc != ESI_OK)
+            return rc;
     }
     hipEvent_t* pe = nullptr;
     if (st->profiling && st->prof_calls < kProfMax) {
@@ -487,3 +512,210 @@ esi_status esi_get_size(const esi_state* st, int32_t* width, int32_t* height)
 }
 
 }  // extern "C"
+
+// ---- batched calls ----------------------------------------------------------
+
+namespace {
+
+size_t batch_items_bytes(int32_t m) { return align_up(sizeof(BatchItem) * (size_t)m, 256); }
+size_t batch_base_bytes(int32_t m) { return align_up(sizeof(uint32_t) * ((size_t)m + 1), 256); }
+size_t batch_bytes(int32_t m) { return batch_items_bytes(m) + 3 * batch_base_bytes(m); }
+
+void batch_free(esi_batch* b)
+{
+    if (b->copied)
+        (void)hipEventDestroy(b->copied);
+    if (b->dev)
+        (void)hipFree(b->dev);
+    if (b->host)
+        (void)hipHostFree(b->host);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+esi_status esi_batch_create(int32_t max_items, esi_batch** out)
+{
+    if (!out)
+        return ESI_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (max_items < 1 || max_items > kMaxBatch)
+        return ESI_ERR_INVALID_ARG;
+    esi_batch* b = new (std::nothrow) esi_batch();
+    if (!b)
+        return ESI_ERR_OUT_OF_MEMORY;
+    b->max_items = max_items;
+    b->bytes = batch_bytes(max_items);
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return ESI_ERR_HIP;
+    }
+    if (hipHostMalloc(&b->host, b->bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&b->dev, b->bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return ESI_ERR_OUT_OF_MEMORY;
+    }
+    if (hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+        b->copied = nullptr;
+        batch_free(b);
+        return ESI_ERR_HIP;
+    }
+    *out = b;
+    return ESI_OK;
+}
+
+esi_status esi_batch_destroy(esi_batch* b)
+{
+    if (!b)
+        return ESI_ERR_INVALID_ARG;
+    DeviceGuard g(b->device);
+    esi_status rc = ESI_OK;
+    // kernels of earlier calls may still read the device descriptors
+    if (hipDeviceSynchronize() != hipSuccess)
+        rc = ESI_ERR_HIP;
+    batch_free(b);
+    return rc;
+}
+
+esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* states,
+                               const esi_events* events, const int64_t* const* t_frames,
+                               const int32_t* n_frames, float* const* frames,
+                               uint8_t* const* frames_u8, hipStream_t stream)
+{
+    if (!b || !states || !events || n_items < 1 || n_items > b->max_items)
+        return ESI_ERR_INVALID_ARG;
+    // every item checked as esi_integrate_window checks its arguments
+    int64_t n_all = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const esi_state* st = states[i];
+        const esi_events& ev = events[i];
+        const int32_t nf = n_frames ? n_frames[i] : 0;
+        const int64_t* tf = t_frames ? t_frames[i] : nullptr;
+        const float* fr = frames ? frames[i] : nullptr;
+        const uint8_t* u8 = frames_u8 ? frames_u8[i] : nullptr;
+        if (!st || st->device != b->device || nf < 0)
+            return ESI_ERR_INVALID_ARG;
+        if (ev.n > 0 && (!ev.x || !ev.y || !ev.t || !ev.p))
+            return ESI_ERR_INVALID_ARG;
+        if (ev.n >= ((size_t)1 << 31))
+            return ESI_ERR_INVALID_ARG;
+        if ((nf > 0) != (tf != nullptr) || (nf > 0 && !fr && !u8))
+            return ESI_ERR_INVALID_ARG;
+        n_all += (int64_t)ev.n;
+    }
+    {
+        // one state at most once: its items would race
+        std::vector<const esi_state*> seen(states, states + n_items);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            return ESI_ERR_INVALID_ARG;
+    }
+    for (int32_t i = 0; i < n_items; ++i)
+        if (states[i]->poisoned)
+            return ESI_ERR_POISONED;
+    DeviceGuard g(b->device);
+
+    // schedules: the bucketing ranges shared out by event count
+    std::vector<Schedule> sc(n_items);
+    int kmax = 1;
+    for (int32_t i = 0; i < n_items; ++i) {
+        sc[i] = make_schedule(states[i]->npix, 0, 1);
+        if (events[i].n > 0)
+            kmax = std::max(kmax, sc[i].ntiles);
+    }
+    const int slots = bucket_slots(kmax);
+    std::vector<BatchItem> it(n_items);
+    std::vector<int> cls(n_items);  // integration class: tile size and decay kind
+    for (int32_t i = 0; i < n_items; ++i) {
+        esi_state* st = states[i];
+        const int64_t n = (int64_t)events[i].n;
+        const int share =
+            n > 0 ? std::max(1, (int)((double)slots * (double)n / (double)n_all)) : 1;
+        sc[i] = make_schedule(st->npix, n, share);
+        BatchItem& x = it[i];
+        x = BatchItem{};
+        x.ev = EventsDev{events[i].x, events[i].y, events[i].t, events[i].p, n};
+        x.st = st->dev;
+        x.mp = method_params(st->params);
+        if (!st->state_in_range)
+            x.mp.need_clamp = 1;
+        const int32_t nf = n_frames ? n_frames[i] : 0;
+        x.fo = FrameOut{nf > 0 ? t_frames[i] : nullptr, nf,
+                        (nf > 0 && frames) ? frames[i] : nullptr,
+                        (nf > 0 && frames_u8) ? frames_u8[i] : nullptr};
+        x.diag = st->diag;
+        x.tile_log = sc[i].tile_log;
+        x.K = sc[i].ntiles;
+        if (n > 0) {
+            const esi_status rc = call_scratch(st, sc[i], n, stream, x.cs);
+            if (rc != ESI_OK)
+                return rc;
+            x.E = sc[i].unit_events;
+            x.B = sc[i].nunits;
+            x.B_pad = (x.B + 7) / 8 * 8;
+            x.nseg = (int)scan_segments(x.B);
+            x.cols = (x.K + 255) / 256;
+        }
+        cls[i] = sc[i].ppt * 8 + decay_kind(x.mp);
+    }
+    // items ordered by class, so that each integration launch covers a range
+    std::vector<int> order(n_items);
+    for (int32_t i = 0; i < n_items; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cls[a] < cls[c]; });
+
+    // the previous call's staging copy must have been read before reuse
+    if (b->pending && hipEventSynchronize(b->copied) != hipSuccess)
+        return ESI_ERR_HIP;
+    b->pending = false;
+    char* h = (char*)b->host;
+    BatchItem* hi = (BatchItem*)h;
+    uint32_t* ub = (uint32_t*)(h + batch_items_bytes(b->max_items));
+    uint32_t* sb = (uint32_t*)((char*)ub + batch_base_bytes(b->max_items));
+    uint32_t* tb = (uint32_t*)((char*)sb + batch_base_bytes(b->max_items));
+    ub[0] = sb[0] = tb[0] = 0;
+    for (int32_t k = 0; k < n_items; ++k) {
+        const BatchItem& x = it[order[k]];
+        hi[k] = x;
+        ub[k + 1] = ub[k] + (uint32_t)x.B_pad;
+        sb[k + 1] = sb[k] + (uint32_t)(x.cols * x.nseg);
+        tb[k + 1] = tb[k] + (uint32_t)x.K;
+    }
+    const char* d = (const char*)b->dev;
+    BatchDev bd{};
+    bd.items = (const BatchItem*)d;
+    bd.unit_base = (const uint32_t*)(d + ((char*)ub - h));
+    bd.seg_base = (const uint32_t*)(d + ((char*)sb - h));
+    bd.tile_base = (const uint32_t*)(d + ((char*)tb - h));
+    bd.n = n_items;
+    auto fail = [&]() {
+        for (int32_t i = 0; i < n_items; ++i)
+            states[i]->poisoned = true;
+        return ESI_ERR_HIP;
+    };
+    if (hipMemcpyAsync(b->dev, b->host, b->bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipEventRecord(b->copied, stream) != hipSuccess)
+        return fail();
+    b->pending = true;
+    if (n_all > 0 && launch_bucket_batch(bd, ub[n_items], sb[n_items], kmax, stream) != hipSuccess)
+        return fail();
+    for (int32_t k0 = 0; k0 < n_items;) {
+        int32_t k1 = k0 + 1;
+        while (k1 < n_items && cls[order[k1]] == cls[order[k0]])
+            ++k1;
+        const int c = cls[order[k0]];
+        if (launch_integrate_batch(bd, k0, k1, tb[k0], tb[k1] - tb[k0], c / 8, c % 8, stream) !=
+            hipSuccess)
+            return fail();
+        k0 = k1;
+    }
+    for (int32_t i = 0; i < n_items; ++i)
+        states[i]->calls++;
+    return ESI_OK;
+}
+
+}  // extern "C"
+

@@ -61,15 +61,14 @@ __device__ __forceinline__ bool valid_q(uint32_t x, uint32_t y, int W, int H, ui
 // Range `unit` holds events [unit E, min((unit + 1) E, n)); E is a multiple
 // of kBlock.
 // Workgroup 0 also clears the per-tile totals that k_seg_sum accumulates.
-__global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int tile_log, int K,
-                                                 int64_t E, uint32_t* table, uint32_t* tile_tot,
-                                                 DiagDev* diag)
+__device__ __forceinline__ void hist_body(const EventsDev& ev, int W, int H, int tile_log, int K,
+                                          int64_t E, uint32_t* table, uint32_t* tile_tot,
+                                          DiagDev* diag, int64_t unit, bool first)
 {
     extern __shared__ uint32_t h[];
-    const int64_t unit = xcd_block(blockIdx.x, gridDim.x);
     for (int k = threadIdx.x; k < K; k += kBlock) {
         h[k] = 0;
-        if (blockIdx.x == 0)
+        if (first)
             tile_tot[k] = 0;
     }
     __syncthreads();
@@ -121,11 +120,10 @@ __global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int
 // (unit u, tile k) = (tiles before k) + (segments before u's) + (rows of u's
 // segment before u), written over table[u][k].
 
-__global__ __launch_bounds__(kBlock) void k_seg_sum(const uint32_t* table, int K, int64_t B,
-                                                    uint32_t* segsum, uint32_t* tile_tot)
+__device__ __forceinline__ void seg_sum_body(const uint32_t* table, int K, int64_t B,
+                                             uint32_t* segsum, uint32_t* tile_tot, int bx, int s)
 {
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    const int s = blockIdx.y;
+    const int k = bx * kBlock + threadIdx.x;
     if (k >= K)
         return;
     const int64_t u0 = (int64_t)s * kSegRows;
@@ -142,10 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_sum(const uint32_t* table, int K
         atomicAdd(&tile_tot[k], sum);
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int64_t B,
-                                                     const uint32_t* segsum,
-                                                     const uint32_t* tile_tot, uint32_t* total,
-                                                     DiagDev* diag)
+__device__ __forceinline__ void seg_down_body(uint32_t* table, int K, int64_t B,
+                                              const uint32_t* segsum, const uint32_t* tile_tot,
+                                              uint32_t* total, DiagDev* diag, int bx, int s)
 {
     constexpr int kBatch = 16;
     constexpr int kPer = (kMaxTiles + kBlock - 1) / kBlock;  // tile totals per thread
@@ -183,13 +180,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int
         run += v[i];
     }
     __syncthreads();
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+    if (bx == 0 && s == 0 && tid == 0) {
         *total = all;
         atomicAdd(&diag->accepted, (unsigned long long)all);
     }
 
-    const int k = blockIdx.x * kBlock + tid;
-    const int s = blockIdx.y;
+    const int k = bx * kBlock + tid;
     if (k >= K)
         return;
     // segments before this one, loads in batches
@@ -219,9 +215,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int
 // ---- stable bucketing, staged in LDS ------------------------------------------
 
 template <int SUB>
-__global__ __launch_bounds__(kBlock, 2) void k_bucket(EventsDev ev, int W, int H, int tile_log,
-                                                   int K, int64_t E, const uint32_t* table,
-                                                   uint64_t* records, int64_t cap, DiagDev* diag)
+__device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, int tile_log, int K,
+                                            int64_t E, const uint32_t* table, uint64_t* records,
+                                            int64_t cap, DiagDev* diag, int64_t unit)
 {
     constexpr int PER_WAVE = SUB / kWavesPerBlock;  // events per wave per sub-batch
     constexpr int STEPS = PER_WAVE / kWave;         // steps of 64 per wave
@@ -246,7 +242,6 @@ __global__ __launch_bounds__(kBlock, 2) void k_bucket(EventsDev ev, int W, int H
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = tid % kWave;
-    const int64_t unit = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t* row = table + unit * K;
     for (int k = tid; k < K; k += kBlock) {
         gbase[k] = row[k];
@@ -414,6 +409,98 @@ __global__ __launch_bounds__(kBlock, 2) void k_bucket(EventsDev ev, int W, int H
     }
 }
 
+// Single-stream kernels: one call's ranges, tile columns and segments.
+__global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int tile_log, int K,
+                                                 int64_t E, uint32_t* table, uint32_t* tile_tot,
+                                                 DiagDev* diag)
+{
+    hist_body(ev, W, H, tile_log, K, E, table, tile_tot, diag, xcd_block(blockIdx.x, gridDim.x),
+              blockIdx.x == 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_sum(const uint32_t* table, int K, int64_t B,
+                                                    uint32_t* segsum, uint32_t* tile_tot)
+{
+    seg_sum_body(table, K, B, segsum, tile_tot, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int64_t B,
+                                                     const uint32_t* segsum,
+                                                     const uint32_t* tile_tot, uint32_t* total,
+                                                     DiagDev* diag)
+{
+    seg_down_body(table, K, B, segsum, tile_tot, total, diag, blockIdx.x, blockIdx.y);
+}
+
+template <int SUB>
+__global__ __launch_bounds__(kBlock, 2) void k_bucket(EventsDev ev, int W, int H, int tile_log,
+                                                   int K, int64_t E, const uint32_t* table,
+                                                   uint64_t* records, int64_t cap, DiagDev* diag)
+{
+    bucket_body<SUB>(ev, W, H, tile_log, K, E, table, records, cap, diag,
+                     xcd_block(blockIdx.x, gridDim.x));
+}
+
+// ---- batched calls: many streams per launch ---------------------------------
+
+// The stream whose work range [base[i], base[i + 1]) holds w (base[0] = 0,
+// non-decreasing; uniform loads).
+__device__ __forceinline__ int batch_item(const uint32_t* base, int n, uint32_t w)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (load_const(base, mid) <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One workgroup per (stream, range); each stream's ranges start at a multiple
+// of the XCD count, so the XCD mapping of one call carries over.
+__global__ __launch_bounds__(kBlock) void kb_hist(BatchDev b)
+{
+    const int i = batch_item(b.unit_base, b.n, blockIdx.x);
+    const BatchItem& it = b.items[i];
+    const int64_t unit = xcd_block(blockIdx.x - load_const(b.unit_base, i), it.B_pad);
+    if (unit >= it.B)
+        return;
+    hist_body(it.ev, it.st.W, it.st.H, it.tile_log, it.K, it.E, it.cs.table, it.cs.tile_tot,
+              it.diag, unit, unit == 0);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_seg_sum(BatchDev b)
+{
+    const int i = batch_item(b.seg_base, b.n, blockIdx.x);
+    const BatchItem& it = b.items[i];
+    const int l = (int)(blockIdx.x - load_const(b.seg_base, i));
+    seg_sum_body(it.cs.table, it.K, it.B, it.cs.blocksum, it.cs.tile_tot, l % it.cols,
+                 l / it.cols);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_seg_down(BatchDev b)
+{
+    const int i = batch_item(b.seg_base, b.n, blockIdx.x);
+    const BatchItem& it = b.items[i];
+    const int l = (int)(blockIdx.x - load_const(b.seg_base, i));
+    seg_down_body(it.cs.table, it.K, it.B, it.cs.blocksum, it.cs.tile_tot, it.cs.total, it.diag,
+                  l % it.cols, l / it.cols);
+}
+
+template <int SUB>
+__global__ __launch_bounds__(kBlock, 2) void kb_bucket(BatchDev b)
+{
+    const int i = batch_item(b.unit_base, b.n, blockIdx.x);
+    const BatchItem& it = b.items[i];
+    const int64_t unit = xcd_block(blockIdx.x - load_const(b.unit_base, i), it.B_pad);
+    if (unit >= it.B)
+        return;
+    bucket_body<SUB>(it.ev, it.st.W, it.st.H, it.tile_log, it.K, it.E, it.cs.table,
+                     it.cs.records, it.ev.n, it.diag, unit);
+}
+
 size_t bucket_lds(int K)
 {
     return sizeof(uint64_t) * (kSub + (size_t)K) + 2 * sizeof(uint32_t) * K +
@@ -436,6 +523,20 @@ int bucket_slots(int K)
 }
 
 size_t scan_segments(int64_t B) { return (size_t)((B + kSegRows - 1) / kSegRows); }
+
+hipError_t launch_bucket_batch(const BatchDev& b, uint32_t units, uint32_t seg_blocks, int kmax,
+                               hipStream_t stream)
+{
+    if (units == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(kb_hist, dim3(units), dim3(kBlock), sizeof(uint32_t) * kmax, stream, b);
+    if (seg_blocks) {
+        hipLaunchKernelGGL(kb_seg_sum, dim3(seg_blocks), dim3(kBlock), 0, stream, b);
+        hipLaunchKernelGGL(kb_seg_down, dim3(seg_blocks), dim3(kBlock), 0, stream, b);
+    }
+    hipLaunchKernelGGL(kb_bucket<kSub>, dim3(units), dim3(kBlock), bucket_lds(kmax), stream, b);
+    return hipGetLastError();
+}
 
 hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                          const CallScratch& cs, DiagDev* diag, hipStream_t stream)

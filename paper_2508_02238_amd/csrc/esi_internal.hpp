@@ -57,6 +57,39 @@ struct StateDev {
     int64_t npix;
 };
 
+// Frames of one call: times (device), count, FP32 and 8-bit outputs (either
+// may be null).
+struct FrameOut {
+    const int64_t* t_frames;
+    int nf;
+    float* frames;
+    uint8_t* frames_u8;
+};
+
+// One stream of a batched call: everything its kernels read, in device
+// memory.  Work of one batched launch is laid out stream by stream; a
+// stream's first work index in each launch is in the base arrays below.
+struct BatchItem {
+    EventsDev ev;
+    StateDev st;
+    MethodParams mp;
+    FrameOut fo;
+    CallScratch cs;  // null pointers when the stream has no events
+    DiagDev* diag;
+    int tile_log, K;  // tile size, tiles
+    int nseg, cols;   // table scan: segments x columns of 256 tiles
+    int64_t E, B;     // events per bucketing range, ranges
+    int64_t B_pad;    // ranges rounded up to a multiple of the XCD count
+};
+
+struct BatchDev {
+    const BatchItem* items;
+    const uint32_t* unit_base;  // [n + 1]: bucketing ranges (padded), stream by stream
+    const uint32_t* seg_base;   // [n + 1]: table-scan workgroups
+    const uint32_t* tile_base;  // [n + 1]: tiles
+    int n;
+};
+
 // Bucketing workgroups the current device holds at once for K tiles.
 int bucket_slots(int K);
 // Segments of the column-wise table scan for B units.
@@ -72,5 +105,13 @@ hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Sched
 hipError_t launch_snapshot(const StateDev& st, const MethodParams& mp, int64_t t_f, float* frame,
                            uint8_t* u8, hipStream_t stream);
 hipError_t launch_reset(const StateDev& st, int64_t t0, DiagDev* diag, hipStream_t stream);
+
+// Batched launches over items [i0, i1) of `b` (the integration launch covers
+// items of one tile size and decay kind; kmax = largest K among them).
+hipError_t launch_bucket_batch(const BatchDev& b, uint32_t units, uint32_t seg_blocks, int kmax,
+                               hipStream_t stream);
+hipError_t launch_integrate_batch(const BatchDev& b, int i0, int i1, uint32_t tile0,
+                                  uint32_t tiles, int ppt, int bk, hipStream_t stream);
+int decay_kind(const MethodParams& mp);
 
 }  // namespace esi

@@ -45,6 +45,8 @@
 // for the stores too.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "esi_internal.hpp"
 
 namespace esi {
@@ -72,13 +74,6 @@ struct TileCfg {
     static constexpr int CHUNK = PPT == 1 ? 1280 : PPT == 2 ? 1536 : 1024;
     static constexpr int PER_WAVE = CHUNK / WAVES;  // records per wave per chunk
     static constexpr int STEPS = PER_WAVE / kWave;  // records per lane per chunk
-};
-
-struct FrameOut {
-    const int64_t* t_frames;
-    int nf;
-    float* frames;
-    uint8_t* frames_u8;
 };
 
 // Number of leading entries of tfl[0, n) that are < t (n <= kFrameGroup), in
@@ -300,10 +295,12 @@ template <int PPT, int NB>
 constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : PPT == 2 ? 4 : 1; }
 
 template <int PPT, int NB, int BK>
-__global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrate(
-    const uint64_t* __restrict__ records, const uint32_t* __restrict__ table,
-    const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t, int K, StateDev st,
-    MethodParams mp, FrameOut fo, DiagDev* diag)
+__device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ records,
+                                               const uint32_t* __restrict__ table,
+                                               const uint32_t* __restrict__ total,
+                                               const int64_t* __restrict__ ev_t, int K,
+                                               StateDev st, MethodParams mp, FrameOut fo,
+                                               DiagDev* diag, int tile)
 {
     using Cfg = TileCfg<PPT, NB>;
     constexpr int TILE = Cfg::TILE;
@@ -336,7 +333,6 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = tid % kWave;
-    const int tile = blockIdx.x;
     const int64_t q0 = (int64_t)tile * TILE + tid;
     const int64_t npix = st.npix;
     const int nf = fo.nf;
@@ -702,6 +698,53 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
     }
 }
 
+// One workgroup per tile of one call.
+template <int PPT, int NB, int BK>
+__global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrate(
+    const uint64_t* __restrict__ records, const uint32_t* __restrict__ table,
+    const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t, int K, StateDev st,
+    MethodParams mp, FrameOut fo, DiagDev* diag)
+{
+    integrate_body<PPT, NB, BK>(records, table, total, ev_t, K, st, mp, fo, diag, blockIdx.x);
+}
+
+// Batched: the tiles of items [i0, i1) (one tile size and decay kind), work
+// indices [tile0, tile0 + tiles) laid out item by item; each workgroup takes
+// a contiguous share of them, so it looks its item up once and then only
+// steps to the next item.
+template <int PPT, int NB, int BK>
+__global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void kb_integrate(
+    BatchDev b, int i0, int i1, uint32_t tile0, uint32_t tiles)
+{
+    const uint32_t per = (tiles + gridDim.x - 1) / gridDim.x;
+    uint32_t w = tile0 + blockIdx.x * per;
+    const uint32_t w_end = min(tile0 + tiles, w + per);
+    if (w >= w_end)
+        return;
+    // the item holding w: the last with tile_base <= w
+    int lo = i0, hi = i1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (load_const(b.tile_base, mid) <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    int i = lo;
+    uint32_t first = load_const(b.tile_base, i), next = load_const(b.tile_base, i + 1);
+    for (; w < w_end; ++w) {
+        while (w >= next) {
+            ++i;
+            first = next;
+            next = load_const(b.tile_base, i + 1);
+        }
+        const BatchItem& it = b.items[i];
+        integrate_body<PPT, NB, BK>(it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K, it.st,
+                                    it.mp, it.fo, it.diag, (int)(w - first));
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
 template <int BK>
 __global__ __launch_bounds__(kBlock) void k_snapshot(StateDev st, MethodParams mp, int64_t t_f,
                                                      float* frame, uint8_t* u8)
@@ -734,12 +777,6 @@ __global__ __launch_bounds__(kBlock) void k_reset(StateDev st, int64_t t0, DiagD
     }
 }
 
-int decay_kind(const MethodParams& mp)
-{
-    if (mp.exp_decay)
-        return kDecayExp;
-    return mp.b == 1.0 ? kDecayB1 : (mp.b == 2.0 ? kDecayB2 : kDecayPow);
-}
 
 template <int PPT, int NB, int BK>
 hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Schedule& sc,
@@ -779,6 +816,13 @@ hipError_t launch_integrate_p(const EventsDev& ev, const StateDev& st, const Sch
 
 }  // namespace
 
+int decay_kind(const MethodParams& mp)
+{
+    if (mp.exp_decay)
+        return kDecayExp;
+    return mp.b == 1.0 ? kDecayB1 : (mp.b == 2.0 ? kDecayB2 : kDecayPow);
+}
+
 hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                             const CallScratch& cs, const MethodParams& mp,
                             const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
@@ -798,6 +842,62 @@ hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Sched
     case 8:
         return launch_integrate_p<8, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
                                           stream);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+
+template <int PPT, int BK>
+hipError_t launch_integrate_batch_t(const BatchDev& b, int i0, int i1, uint32_t tile0,
+                                    uint32_t tiles, hipStream_t stream)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb_integrate<PPT, 256, BK>, 256, 0) !=
+            hipSuccess)
+        return hipGetLastError();
+    // a few workgroups per slot: contiguous shares, balanced by the dispatcher
+    const uint32_t grid = std::min<uint32_t>(tiles, 4u * (uint32_t)std::max(1, cus * per_cu));
+    hipLaunchKernelGGL((kb_integrate<PPT, 256, BK>), dim3(grid), dim3(256), 0, stream, b, i0, i1,
+                       tile0, tiles);
+    return hipGetLastError();
+}
+
+template <int PPT>
+hipError_t launch_integrate_batch_p(const BatchDev& b, int i0, int i1, uint32_t tile0,
+                                    uint32_t tiles, int bk, hipStream_t stream)
+{
+    switch (bk) {
+    case kDecayB1:
+        return launch_integrate_batch_t<PPT, kDecayB1>(b, i0, i1, tile0, tiles, stream);
+    case kDecayB2:
+        return launch_integrate_batch_t<PPT, kDecayB2>(b, i0, i1, tile0, tiles, stream);
+    case kDecayExp:
+        return launch_integrate_batch_t<PPT, kDecayExp>(b, i0, i1, tile0, tiles, stream);
+    default:
+        return launch_integrate_batch_t<PPT, kDecayPow>(b, i0, i1, tile0, tiles, stream);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_integrate_batch(const BatchDev& b, int i0, int i1, uint32_t tile0,
+                                  uint32_t tiles, int ppt, int bk, hipStream_t stream)
+{
+    if (tiles == 0)
+        return hipSuccess;
+    switch (ppt) {
+    case 1:
+        return launch_integrate_batch_p<1>(b, i0, i1, tile0, tiles, bk, stream);
+    case 2:
+        return launch_integrate_batch_p<2>(b, i0, i1, tile0, tiles, bk, stream);
+    case 4:
+        return launch_integrate_batch_p<4>(b, i0, i1, tile0, tiles, bk, stream);
+    case 8:
+        return launch_integrate_batch_p<8>(b, i0, i1, tile0, tiles, bk, stream);
     default:
         return hipErrorInvalidValue;
     }

@@ -58,3 +58,14 @@ def test_null_state_is_rejected():
     assert esi.esi_destroy_state(None) == esi.ESI_ERR_INVALID_ARG
     assert esi.esi_snapshot_frame(None, 0, None, None, 0) == esi.ESI_ERR_INVALID_ARG
     assert esi.esi_state_bytes(None) == 0
+
+
+def test_batch_rejects_invalid_arguments():
+    """Checked on the host before any HIP call, so this runs without a GPU."""
+    import paper_2508_02238_amd as esi
+    for m in (0, -1, 4097):
+        rc, h = esi.esi_batch_create(m)
+        assert rc == esi.ESI_ERR_INVALID_ARG and h is None
+    assert esi.esi_batch_destroy(None) == esi.ESI_ERR_INVALID_ARG
+    assert esi.esi_integrate_batch(None, [None], [(None, None, None, None, 0)]) == \
+        esi.ESI_ERR_INVALID_ARG

@@ -69,7 +69,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--fps", type=float, default=100.0)
     ap.add_argument("--u8", action="store_true", help="also write 8-bit frames")
     ap.add_argument("--u8-only", action="store_true", help="write 8-bit frames only")
@@ -100,6 +100,8 @@ def main() -> int:
     import paper_2508_02238_amd as esi
 
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        return bench_batched(args)
     t0 = time.time()
     s = evgen.preset(args.workload)
     tf = s.frame_times(args.fps)
@@ -268,6 +270,169 @@ def main() -> int:
         "cpu_baseline": cpu,
     }
     st.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batched(args) -> int:
+    """Workload c4: 64 independent streams of mixed size and rate, integrated
+    window by window (10 ms of events and one frame per stream per window),
+    once with one batched call per window and once with one plain call per
+    stream per window.  A step is the whole sample (all windows); states are
+    reset before each step, outside the timed region."""
+    import numpy as np
+    import torch
+
+    import evgen
+    import paper_2508_02238_amd as esi
+
+    win_us = 10_000
+    dur_us = 200_000
+    t0 = time.time()
+    streams = evgen.preset_batch("c4", duration_us=dur_us)
+    nwin = dur_us // win_us
+    n_all = sum(s.n for s in streams)
+    px_all = sum(s.width * s.height for s in streams)
+    log(f"[bench] workload c4: {len(streams)} streams, {px_all} pixels, {n_all} events in "
+        f"{nwin} windows of {win_us / 1000:g} ms (generated in {time.time() - t0:.1f} s)")
+    prm = dict(evgen.DEFAULT_PARAMS)
+    prm["flags"] = args.flags
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    ev_d, bounds, frames, tfs = [], [], [], []
+    for s in streams:
+        ev_d.append((torch.from_numpy(s.x.view(np.int16)).to(dev),
+                     torch.from_numpy(s.y.view(np.int16)).to(dev),
+                     torch.from_numpy(s.t).to(dev), torch.from_numpy(s.p).to(dev)))
+        bounds.append(np.searchsorted(s.t, np.arange(nwin + 1) * win_us, side="left"))
+        frames.append(torch.empty((1, s.height, s.width), dtype=torch.float32, device=dev))
+    tf_d = torch.tensor([(w + 1) * win_us - 1 for w in range(nwin)], dtype=torch.int64,
+                        device=dev)
+    states = [esi.State(s.width, s.height, **prm) for s in streams]
+    batch = esi.Batch(len(streams))
+
+    def items(w):
+        evs, tfp = [], []
+        for i, (x, y, t, p) in enumerate(ev_d):
+            lo, hi = int(bounds[i][w]), int(bounds[i][w + 1])
+            n = hi - lo
+            evs.append((x.data_ptr() + 2 * lo, y.data_ptr() + 2 * lo, t.data_ptr() + 8 * lo,
+                        p.data_ptr() + lo, n) if n else (None, None, None, None, 0))
+        return evs
+
+    win_items = [items(w) for w in range(nwin)]
+    handles = [s.handle for s in states]
+    frp = [f.data_ptr() for f in frames]
+
+    def run_batched():
+        for w in range(nwin):
+            rc = esi.esi_integrate_batch(batch.handle, handles, win_items[w],
+                                         [tf_d.data_ptr() + 8 * w] * len(states),
+                                         [1] * len(states), frp, None, stream)
+            assert rc == esi.ESI_OK, esi.esi_status_string(rc)
+
+    def run_plain():
+        for w in range(nwin):
+            for i, h in enumerate(handles):
+                e = win_items[w][i]
+                rc = esi.esi_integrate_window(h, *e, tf_d.data_ptr() + 8 * w, 1, frp[i], None,
+                                              stream)
+                assert rc == esi.ESI_OK, esi.esi_status_string(rc)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            for s in states:
+                s.reset()
+            fn()
+        torch.cuda.synchronize()
+        total = 0.0
+        for _ in range(steps):
+            for s in states:
+                s.reset()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            total += e0.elapsed_time(e1)
+        return total / steps
+
+    ms_batch = timed(run_batched, args.steps, args.warmup)
+    ms_plain = timed(run_plain, args.steps, args.warmup)
+    log(f"[bench] per window: batched {ms_batch / nwin * 1e3:.1f} us, "
+        f"plain {ms_plain / nwin * 1e3:.1f} us ({len(streams)} calls)")
+
+    parity = None
+    if not args.no_parity:
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from esi_parity import REL
+        for s in states:
+            s.reset()
+        run_batched()
+        torch.cuda.synchronize()
+        worst_s = worst_f = 0.0
+        exact = True
+        pick = sorted(set([0, len(streams) // 2, len(streams) - 1]))
+        floor_f = prm["C"] / (prm["s_max"] - prm["s_min"])
+        for i in pick:
+            s = streams[i]
+            o = oracle.State(s.width, s.height, oracle.Params(**prm))
+            fo = o.integrate(s.x, s.y, s.t, s.p, t_frames=np.array([dur_us - 1], np.int64))
+            S, T, N, P = (a.cpu().numpy() for a in states[i].read_state())
+            exact &= (np.array_equal(N.view(np.uint32), o.N) and np.array_equal(P, o.P)
+                      and np.array_equal(T, o.T))
+            worst_s = max(worst_s, float((np.abs(S.astype(np.float64) - o.S)
+                                          / np.maximum(np.abs(o.S), prm["C"])).max()))
+            fg = frames[i].cpu().numpy()
+            worst_f = max(worst_f, float((np.abs(fg.astype(np.float64) - fo)
+                                          / np.maximum(np.abs(fo), floor_f)).max()))
+        parity = {"ok": bool(exact and worst_s <= REL and worst_f <= REL),
+                  "streams_checked": pick, "max_rel_S": worst_s, "max_rel_frame": worst_f,
+                  "exact_N_P_T": bool(exact)}
+        log(f"[bench] parity vs oracle: {parity}")
+
+    # per window: events read, S and T of
+    # every pixel read for the frame, the full state of the active pixels
+    # read and written (N, P read; S, T, N, P written), one FP32 frame
+    active = 0
+    for i, s in enumerate(streams):
+        q = s.y.astype(np.int64) * s.width + s.x
+        for w in range(nwin):
+            active += np.unique(q[bounds[i][w]:bounds[i][w + 1]]).size
+    alg = 13 * n_all + nwin * (12 + 4) * px_all + 28 * active
+    out = {
+        "metric": "Gevents/s integrated + frames/s at 1e-5 rel err (batched streams)",
+        "value": round(n_all / (ms_batch * 1e-3) / 1e9, 3),
+        "unit": "Gevents/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batch, 4),
+        "us_per_window": round(ms_batch / nwin * 1e3, 1),
+        "plain_us_per_window": round(ms_plain / nwin * 1e3, 1),
+        "batched_over_plain": round(ms_plain / ms_batch, 3),
+        "frames_per_s": round(len(streams) * nwin / (ms_batch * 1e-3), 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"c4: {len(streams)} streams (346x260, 640x480, 1280x720), "
+                               f"{n_all} events in {nwin} windows of 10 ms, one frame per "
+                               f"stream per window",
+                   "streams": len(streams), "pixels": px_all, "events": n_all,
+                   "windows": nwin, "params": prm},
+        "roofline_path": {"achieved": round(alg / (ms_batch * 1e-3) / 1e9, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(alg / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "algorithmic_bytes": alg},
+        "parity": parity,
+    }
+    batch.close()
+    for s in states:
+        s.close()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -199,6 +199,51 @@ def preset(name: str, **overrides) -> Stream:
 
 
 # ---------------------------------------------------------------------------
+# Many independent streams (batched workload)
+# ---------------------------------------------------------------------------
+
+# Per resolution: the scene of the single-stream workload of that size, its
+# event rate at the stored parameters (events/s), and the scene parameter
+# that the rate scales with (event counts grow linearly with it).
+_BATCH_SCENES = {
+    (346, 260): ("c1", 1.0e6, "grating_speed_px_s"),
+    (640, 480): ("c2", 1.99e6, "tex_speed_px_s"),
+    (1280, 720): ("c3", 30.6e6, "spoke_rev_s"),
+}
+
+
+def preset_batch(name: str = "c4", duration_us: int = 200_000, n_streams: int = 64,
+                 threads: int | None = None) -> list[Stream]:
+    """The batched workload: n_streams independent streams, resolution drawn
+    uniformly from 346x260, 640x480 and 1280x720, event rate lognormal with
+    median 1.41 Mevents/s and sigma 1.03 (0.1 and 20 Mevents/s at the 0.5%
+    and 99.5% points), clipped to [0.1, 20] Mevents/s; each stream is the
+    scene of the single-stream workload of its size with its speed scaled to
+    the drawn rate (not re-tuned: rates land near the target).  Stream s uses
+    seed 4000 + s (workload 4)."""
+    if name != "c4":
+        raise KeyError(name)
+    rng = np.random.default_rng(4)
+    sizes = list(_BATCH_SCENES)
+    out = []
+    for s in range(n_streams):
+        W, H = sizes[int(rng.integers(0, len(sizes)))]
+        rate = float(np.clip(rng.lognormal(np.log(1.41e6), 1.03), 0.1e6, 20e6))
+        base, base_rate, knob = _BATCH_SCENES[(W, H)]
+        spec = PRESETS[base]
+        # the noise share is taken of target_scene_events: scaled to this
+        # stream's scene events
+        scene_events = rate * duration_us * 1e-6 * (1.0 - spec.noise_fraction)
+        spec = StreamSpec(**{**spec.__dict__, "duration_us": int(duration_us),
+                             "seed": 4000 + s, "target_scene_events": scene_events,
+                             knob: getattr(spec, knob) * rate / base_rate})
+        st = generate(spec, threads=threads)
+        st.meta.update({"target_rate": rate, "base": base})
+        out.append(st)
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Small adversarial streams for tests (numpy, seeded)
 # ---------------------------------------------------------------------------
 

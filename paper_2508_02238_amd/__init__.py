@@ -13,6 +13,10 @@ from __future__ import annotations
 import ctypes
 import os
 
+# torch first: it brings the HIP runtime its device memory and streams live
+# in, and the library must bind to that same runtime
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesi.so")
 

@@ -97,8 +97,8 @@ struct Pixels {
     // state after every event applied so far (Alg. 2)
     double S[PPT];
     int64_t T[PPT];
-    uint32_t N[PPT];
-    int32_t P[PPT];
+    uint32_t N[PPT];  // events of this call (added to the stored count at the end)
+    int32_t P[PPT];   // their polarity sum
     // the state the frames see: Sv = S / (s_max - s_min) and Av = 1 + k (T - t_b)
     // (exponential decay: Av = exp(k (T - t_b)))
     double Sv[PPT], Av[PPT];
@@ -348,8 +348,8 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
         in[i] = q < npix;
         px.S[i] = in[i] ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
         px.T[i] = in[i] ? st.T[q] : 0;
-        px.N[i] = in[i] ? st.N[q] : 0u;
-        px.P[i] = in[i] ? st.P[q] : 0;
+        px.N[i] = 0u;  // this call's events and polarity sum; added to N, P at the end
+        px.P[i] = 0;
     }
 
     // the tile's records [rs, re); read-only here, so scalar loads
@@ -677,13 +677,15 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int64_t q = q0 + (int64_t)i * NB;
-        if (in[i]) {
+        // a pixel without events in this call keeps its stored state as it
+        // is (S, T unchanged, no re-rounding), so only touched pixels write
+        if (in[i] && px.N[i] != 0u) {
             const float hi = (float)px.S[i];
             st.S_hi[q] = hi;
             st.S_lo[q] = (float)(px.S[i] - (double)hi);
             st.T[q] = px.T[i];
-            st.N[q] = px.N[i];
-            st.P[q] = px.P[i];
+            st.N[q] += px.N[i];
+            st.P[q] += px.P[i];
         }
     }
     if (bad)

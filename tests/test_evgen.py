@@ -114,3 +114,18 @@ def test_preset_metadata(name):
     spec = evgen.PRESETS[name]
     assert spec.width * spec.height in (346 * 260, 640 * 480, 1280 * 720)
     assert spec.seed == {"c1": 1, "c2": 2, "c3": 3}[name]
+
+
+def test_batched_workload_shape():
+    """Workload c4: 64 streams, sizes from the three single-stream workloads,
+    seeded (same streams twice), rates spread over two orders of magnitude."""
+    a = evgen.preset_batch("c4", duration_us=20_000)
+    b = evgen.preset_batch("c4", duration_us=20_000)
+    assert len(a) == 64
+    assert {(s.width, s.height) for s in a} <= {(346, 260), (640, 480), (1280, 720)}
+    for s, u in zip(a, b):
+        assert s.n == u.n and np.array_equal(s.t, u.t) and np.array_equal(s.x, u.x)
+        assert np.all(np.diff(s.t) >= 0)
+    rates = np.array([s.meta["target_rate"] for s in a])
+    assert rates.min() >= 0.1e6 and rates.max() <= 20e6
+    assert 0.5e6 < np.median(rates) < 3e6

@@ -61,12 +61,13 @@ __device__ __forceinline__ bool valid_q(uint32_t x, uint32_t y, int W, int H, ui
 // Range `unit` holds events [unit E, min((unit + 1) E, n)); E is a multiple
 // of kBlock.
 // Workgroup 0 also clears the per-tile totals that k_seg_sum accumulates.
+template <int NT>
 __device__ __forceinline__ void hist_body(const EventsDev& ev, int W, int H, int tile_log, int K,
                                           int64_t E, uint32_t* table, uint32_t* tile_tot,
                                           DiagDev* diag, int64_t unit, bool first)
 {
     extern __shared__ uint32_t h[];
-    for (int k = threadIdx.x; k < K; k += kBlock) {
+    for (int k = threadIdx.x; k < K; k += NT) {
         h[k] = 0;
         if (first)
             tile_tot[k] = 0;
@@ -79,7 +80,7 @@ __device__ __forceinline__ void hist_body(const EventsDev& ev, int W, int H, int
     int64_t i = lo;
     if (vec) {
         // 8 events per thread per step: 16-byte loads of x and y
-        for (; i + 8 * kBlock <= hi; i += 8 * kBlock) {
+        for (; i + 8 * NT <= hi; i += 8 * NT) {
             const int64_t e = i + 8 * threadIdx.x;
             const uint4 xv = *(const uint4*)(ev.x + e);
             const uint4 yv = *(const uint4*)(ev.y + e);
@@ -99,7 +100,7 @@ __device__ __forceinline__ void hist_body(const EventsDev& ev, int W, int H, int
             }
         }
     }
-    for (int64_t e = i + threadIdx.x; e < hi; e += kBlock) {
+    for (int64_t e = i + threadIdx.x; e < hi; e += NT) {
         uint32_t q;
         if (valid_q(ev.x[e], ev.y[e], W, H, q))
             atomicAdd(&h[q >> tile_log], 1u);
@@ -108,7 +109,7 @@ __device__ __forceinline__ void hist_body(const EventsDev& ev, int W, int H, int
     }
     __syncthreads();
     uint32_t* row = table + unit * K;
-    for (int k = threadIdx.x; k < K; k += kBlock)
+    for (int k = threadIdx.x; k < K; k += NT)
         row[k] = h[k];
     if (drop)
         atomicAdd(&diag->dropped, (unsigned long long)drop);
@@ -410,11 +411,15 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
 }
 
 // Single-stream kernels: one call's ranges, tile columns and segments.
-__global__ __launch_bounds__(kBlock) void k_hist(EventsDev ev, int W, int H, int tile_log, int K,
-                                                 int64_t E, uint32_t* table, uint32_t* tile_tot,
-                                                 DiagDev* diag)
+// The histogram runs 1024 threads per range: one workgroup per range, and
+// the ranges are as few as the bucketing workgroups resident at once.
+constexpr int kHistBlock = 1024;
+
+__global__ __launch_bounds__(kHistBlock) void k_hist(EventsDev ev, int W, int H, int tile_log,
+                                                     int K, int64_t E, uint32_t* table,
+                                                     uint32_t* tile_tot, DiagDev* diag)
 {
-    hist_body(ev, W, H, tile_log, K, E, table, tile_tot, diag, xcd_block(blockIdx.x, gridDim.x),
+    hist_body<kHistBlock>(ev, W, H, tile_log, K, E, table, tile_tot, diag, xcd_block(blockIdx.x, gridDim.x),
               blockIdx.x == 0);
 }
 
@@ -460,14 +465,14 @@ __device__ __forceinline__ int batch_item(const uint32_t* base, int n, uint32_t 
 
 // One workgroup per (stream, range); each stream's ranges start at a multiple
 // of the XCD count, so the XCD mapping of one call carries over.
-__global__ __launch_bounds__(kBlock) void kb_hist(BatchDev b)
+__global__ __launch_bounds__(kHistBlock) void kb_hist(BatchDev b)
 {
     const int i = batch_item(b.unit_base, b.n, blockIdx.x);
     const BatchItem& it = b.items[i];
     const int64_t unit = xcd_block(blockIdx.x - load_const(b.unit_base, i), it.B_pad);
     if (unit >= it.B)
         return;
-    hist_body(it.ev, it.st.W, it.st.H, it.tile_log, it.K, it.E, it.cs.table, it.cs.tile_tot,
+    hist_body<kHistBlock>(it.ev, it.st.W, it.st.H, it.tile_log, it.K, it.E, it.cs.table, it.cs.tile_tot,
               it.diag, unit, unit == 0);
 }
 
@@ -529,7 +534,7 @@ hipError_t launch_bucket_batch(const BatchDev& b, uint32_t units, uint32_t seg_b
 {
     if (units == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(kb_hist, dim3(units), dim3(kBlock), sizeof(uint32_t) * kmax, stream, b);
+    hipLaunchKernelGGL(kb_hist, dim3(units), dim3(kHistBlock), sizeof(uint32_t) * kmax, stream, b);
     if (seg_blocks) {
         hipLaunchKernelGGL(kb_seg_sum, dim3(seg_blocks), dim3(kBlock), 0, stream, b);
         hipLaunchKernelGGL(kb_seg_down, dim3(seg_blocks), dim3(kBlock), 0, stream, b);
@@ -544,7 +549,7 @@ hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule
     const int K = sc.ntiles;
     const int64_t B = sc.nunits;
     const int nseg = (int)scan_segments(B);
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)B), dim3(kBlock), sizeof(uint32_t) * K, stream, ev,
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)B), dim3(kHistBlock), sizeof(uint32_t) * K, stream, ev,
                        st.W, st.H, sc.tile_log, K, sc.unit_events, cs.table, cs.tile_tot, diag);
     const dim3 grid((unsigned)((K + kBlock - 1) / kBlock), (unsigned)nseg);
     hipLaunchKernelGGL(k_seg_sum, grid, dim3(kBlock), 0, stream, cs.table, K, B, cs.blocksum,

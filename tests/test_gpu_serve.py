@@ -1,0 +1,91 @@
+"""Served integration: sessions fed packet by packet through the server
+(one batched call per tick, sessions admitted against a memory budget) end
+with the same state and frames as each session integrated alone, one call
+per packet, bit for bit; and latencies are reported for every packet."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import evgen
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(40, 30), (64, 48), (200, 100), (17, 19), (346, 260), (120, 90), (33, 7), (96, 64),
+         (150, 150), (8, 8)]
+PACKET_US = 10_000
+PACKETS = 4
+
+
+@pytest.fixture(scope="module")
+def esi():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2508_02238_amd as m
+    return m
+
+
+def _stream(i, w, h):
+    return evgen.random_stream(seed=900 + i, width=w, height=h, n=2_000 + 300 * i,
+                               t_max=PACKETS * PACKET_US, burst_frac=0.1)
+
+
+def _packet(s, k):
+    lo = int(np.searchsorted(s.t, k * PACKET_US, side="left"))
+    hi = int(np.searchsorted(s.t, (k + 1) * PACKET_US, side="left"))
+    return s.slice(lo, hi), (k + 1) * PACKET_US - 1
+
+
+def test_served_equals_alone(esi):
+    import torch
+    from paper_2508_02238_amd.serve import Server
+    prm = dict(C=0.2, k_per_us=2e-5, b=2.0, s_min=-1.0, s_max=1.0)
+    streams = [_stream(i, w, h) for i, (w, h) in enumerate(SIZES)]
+    # a budget for about half of the sessions' states at once
+    probe = Server(budget_bytes=1 << 40, max_batch=4, max_packet_events=1 << 14)
+    costs = [probe._cost(w, h) for (w, h) in SIZES]
+    probe.close_all()
+    srv = Server(budget_bytes=sum(sorted(costs)[:5]) + costs[4], max_batch=16,
+                 max_packet_events=1 << 14)
+    admitted = [srv.open(i, w, h, **prm) for i, (w, h) in enumerate(SIZES)]
+    assert any(admitted) and not all(admitted)   # the budget is exercised
+    finished = {}
+    sent = [0] * len(SIZES)
+    while len(finished) < len(SIZES):
+        for i in range(len(SIZES)):
+            if i in finished or not srv.admitted(i):
+                continue
+            if sent[i] < PACKETS and not srv.sessions[i].pending:
+                ws, tf = _packet(streams[i], sent[i])
+                srv.submit(i, ws.x, ws.y, ws.t, ws.p, tf, pid=sent[i])
+                sent[i] += 1
+        srv.tick()
+        srv.poll()
+        for i in range(len(SIZES)):
+            if i in finished or not srv.admitted(i) or sent[i] < PACKETS:
+                continue
+            if srv.sessions[i].pending:
+                continue
+            srv.poll(wait=True)
+            st = srv.sessions[i].state
+            finished[i] = ([a.clone() for a in st.read_state()],
+                           srv.sessions[i].frame.clone())
+            torch.cuda.synchronize()
+            srv.close(i)
+    lat = srv.done
+    assert len(lat) == PACKETS * len(SIZES) and all(l >= 0 for _, _, l in lat)
+    srv.close_all()
+    for i, (w, h) in enumerate(SIZES):
+        alone = esi.State(w, h, **prm)
+        fr = None
+        for k in range(PACKETS):
+            ws, tf = _packet(streams[i], k)
+            fr, _ = alone.integrate(ws.x, ws.y, ws.t, ws.p, t_frames=np.array([tf], np.int64))
+        ref = alone.read_state()
+        torch.cuda.synchronize()
+        got_state, got_frame = finished[i]
+        for a, b in zip(got_state, ref):
+            assert torch.equal(a, b), i
+        assert torch.equal(got_frame, fr), i
+        alone.close()

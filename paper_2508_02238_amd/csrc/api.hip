@@ -149,7 +149,7 @@ esi_status call_scratch(esi_state* st, const Schedule& sc, int64_t n, hipStream_
     const size_t need = o_rec + 8 * (size_t)n;
     if (need > st->scratch_bytes) {
         // the old scratch may still be read by work queued on this stream
-        if (hipStreamSynchronize(stream) != hipSuccess)
+        if (st->scratch && hipStreamSynchronize(stream) != hipSuccess)
             return hip_fail(st);
         if (st->scratch)
             (void)hipFree(st->scratch);

@@ -57,7 +57,8 @@ class Server:
         self.batch = Batch(self.max_batch)
         self.compute = torch.cuda.current_stream(self.dev)
         self.copy = torch.cuda.Stream(self.dev)   # default priority
-        self.inflight = collections.deque()  # (event, [(sid, packet id, arrival)], buffers)
+        self.inflight = collections.deque()  # (event, [(sid, packet id, arrival)])
+        self.retiring = collections.deque()  # (event, session) closed, not freed yet
         self.done = []                       # (sid, packet id, latency s)
         self._bufs = [None, None]
         self._flip = 0
@@ -82,15 +83,25 @@ class Server:
         self.used += s.cost
 
     def close(self, sid):
-        """Free a session (after its packets are done) and admit waiting ones."""
+        """Retire a session.  Its memory is freed, and its budget handed to
+        waiting sessions, once the work queued so far has finished (no wait
+        here)."""
         s = self.sessions.pop(sid)
-        if s.state is not None:
-            self.compute.synchronize()
+        if s.state is None:
+            self.waiting.remove(s)
+            return
+        ev = torch.cuda.Event()
+        ev.record(self.compute)
+        self.retiring.append((ev, s))
+        self._reap()
+
+    def _reap(self):
+        while self.retiring and self.retiring[0][0].query():
+            _, s = self.retiring.popleft()
             s.state.close()
             s.state = None
+            s.frame = None
             self.used -= s.cost
-        else:
-            self.waiting.remove(s)
         while self.waiting and self.used + self.waiting[0].cost <= self.budget:
             self._admit(self.waiting.popleft())
 
@@ -189,6 +200,7 @@ class Server:
             self.inflight.popleft()
             out += [(sid, pid, now - arr) for sid, pid, arr in pk]
         self.done += out
+        self._reap()
         return out
 
     def busy(self) -> int:
@@ -198,4 +210,6 @@ class Server:
         self.poll(wait=True)
         for sid in list(self.sessions):
             self.close(sid)
+        self.compute.synchronize()
+        self._reap()
         self.batch.close()

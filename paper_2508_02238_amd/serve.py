@@ -151,6 +151,7 @@ class Server:
         n_all = sum(len(pk[4]) for pk in packets)
         b = self._buffers(n_all)
         hx, hy, ht, hp = (a.numpy() for a in b["h"])
+        htf = b["tf"].numpy()
         off = 0
         offs = []
         for i, pk in enumerate(packets):
@@ -159,7 +160,7 @@ class Server:
             hy[off:off + n] = pk[3].view(np.int16)
             ht[off:off + n] = pk[4]
             hp[off:off + n] = pk[5]
-            b["tf"][i] = pk[6]
+            htf[i] = pk[6]
             offs.append(off)
             off += n
         with torch.cuda.stream(self.copy):

@@ -89,8 +89,9 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE "
-              f"{world}): this build measures the single-GPU path; sharding across GPUs "
-              "is described in DESIGN.md and not built.", file=sys.stderr)
+              f"{world}): this library measures the single-GPU path; sharding across GPUs "
+              "(whole streams per GPU, or row bands with an event exchange) is not built.",
+              file=sys.stderr)
         return 2
 
     import numpy as np

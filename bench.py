@@ -361,10 +361,28 @@ def bench_batched(args) -> int:
             total += e0.elapsed_time(e1)
         return total / steps
 
-    ms_batch = timed(run_batched, args.steps, args.warmup)
+    ms_default = timed(run_batched, args.steps, args.warmup)
     ms_plain = timed(run_plain, args.steps, args.warmup)
-    log(f"[bench] per window: batched {ms_batch / nwin * 1e3:.1f} us, "
-        f"plain {ms_plain / nwin * 1e3:.1f} us ({len(streams)} calls)")
+    # tile sizes per sensor size from the autotuner (throwaway states, the
+    # first three windows); tuning is not timed
+    from paper_2508_02238_amd.tune import tune_tiles
+    h0 = time.time()
+    sample = []
+    for w in range(3):
+        evs = []
+        for i, (x, y, t, p) in enumerate(ev_d):
+            lo, hi = int(bounds[i][w]), int(bounds[i][w + 1])
+            evs.append((x[lo:hi], y[lo:hi], t[lo:hi], p[lo:hi]))
+        sample.append((evs, [tf_d[w:w + 1]] * len(streams)))
+    sizes = [(s.width, s.height) for s in streams]
+    choice = tune_tiles(sizes, prm, sample)
+    for st, sz in zip(states, sizes):
+        st.set_tile_pixels(choice[sz])
+    log(f"[bench] tuned tile pixels {choice} ({time.time() - h0:.1f} s)")
+    ms_batch = timed(run_batched, args.steps, args.warmup)
+    log(f"[bench] per window: batched {ms_batch / nwin * 1e3:.1f} us (default tiles "
+        f"{ms_default / nwin * 1e3:.1f} us), plain {ms_plain / nwin * 1e3:.1f} us "
+        f"({len(streams)} calls)")
 
     parity = None
     if not args.no_parity:
@@ -415,6 +433,8 @@ def bench_batched(args) -> int:
         "ms_per_step": round(ms_batch, 4),
         "us_per_window": round(ms_batch / nwin * 1e3, 1),
         "plain_us_per_window": round(ms_plain / nwin * 1e3, 1),
+        "default_tiles_us_per_window": round(ms_default / nwin * 1e3, 1),
+        "tuned_tile_pixels": {f"{w}x{h}": v for (w, h), v in choice.items()},
         "batched_over_plain": round(ms_plain / ms_batch, 3),
         "frames_per_s": round(len(streams) * nwin / (ms_batch * 1e-3), 1),
         "higher_is_better": True,

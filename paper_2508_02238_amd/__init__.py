@@ -83,6 +83,7 @@ _SIGNATURES = [
                                            ctypes.POINTER(esi_events), ctypes.POINTER(_VP),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_VP),
                                            ctypes.POINTER(_VP), _VP]),
+    ("esi_set_tile_pixels", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("esi_status_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
@@ -143,6 +144,10 @@ def esi_integrate_window(st, x_ptr, y_ptr, t_ptr, p_ptr, n, t_frames_ptr, n_fram
     return lib.esi_integrate_window(_VP(st), ctypes.byref(ev), _VP(t_frames_ptr),
                                     int(n_frames), _VP(frames_ptr), _VP(frames_u8_ptr),
                                     _VP(stream))
+
+
+def esi_set_tile_pixels(st, tile_pixels: int) -> int:
+    return lib.esi_set_tile_pixels(_VP(st), int(tile_pixels))
 
 
 def esi_batch_create(max_items: int):
@@ -335,6 +340,9 @@ class State:
 
     def reset(self):
         _check(esi_reset(self.handle, self._stream()), "esi_reset")
+
+    def set_tile_pixels(self, tile_pixels: int):
+        _check(esi_set_tile_pixels(self.handle, tile_pixels), "esi_set_tile_pixels")
 
     def diagnostics(self) -> dict:
         rc, d = esi_get_diagnostics(self.handle)

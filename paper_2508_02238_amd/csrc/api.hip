@@ -27,6 +27,7 @@ struct esi_state {
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     int bucket_slots = 1024;  // bucketing workgroups resident at once
+    int min_ppt = 1;          // smallest pixels per thread of the integration tiles
     bool state_in_range = true;  // every S in [s_min, s_max] (false after importing one outside)
     bool poisoned = false;
     uint64_t calls = 0;
@@ -93,10 +94,10 @@ MethodParams method_params(const esi_params& p)
 // The split of one call into tiles and bucketing units: the smallest tile
 // (most workgroups) with at most kMaxTiles tiles; the events split evenly over
 // as many bucketing workgroups as the GPU holds at once (`slots`).
-Schedule make_schedule(int64_t npix, int64_t n, int slots)
+Schedule make_schedule(int64_t npix, int64_t n, int slots, int min_ppt = 1)
 {
     Schedule s{};
-    for (int ppt = 1; ppt <= 8; ppt *= 2) {
+    for (int ppt = min_ppt; ppt <= 8; ppt *= 2) {
         s.ppt = ppt;
         s.tile_log = 8 + (ppt == 1 ? 0 : ppt == 2 ? 1 : ppt == 4 ? 2 : 3);
         s.ntiles = (int)((npix + (256 * ppt) - 1) / (256 * ppt));
@@ -343,7 +344,7 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
     MethodParams mp = method_params(st->params);
     if (!st->state_in_range)
         mp.need_clamp = 1;
-    const Schedule sc = make_schedule(st->npix, n, st->bucket_slots);
+    const Schedule sc = make_schedule(st->npix, n, st->bucket_slots, st->min_ppt);
     EventsDev evd{ev->x, ev->y, ev->t, ev->p, n};
     CallScratch cs{};
     if (n > 0) {
@@ -502,6 +503,15 @@ esi_status esi_get_diagnostics(esi_state* st, esi_diag* out)
     return ESI_OK;
 }
 
+esi_status esi_set_tile_pixels(esi_state* st, int32_t tile_pixels)
+{
+    if (!st || !(tile_pixels == 0 || tile_pixels == 256 || tile_pixels == 512 ||
+                 tile_pixels == 1024 || tile_pixels == 2048))
+        return ESI_ERR_INVALID_ARG;
+    st->min_ppt = tile_pixels ? tile_pixels / 256 : 1;
+    return ESI_OK;
+}
+
 esi_status esi_get_size(const esi_state* st, int32_t* width, int32_t* height)
 {
     if (!st || !width || !height)
@@ -622,7 +632,7 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
     std::vector<Schedule> sc(n_items);
     int kmax = 1;
     for (int32_t i = 0; i < n_items; ++i) {
-        sc[i] = make_schedule(states[i]->npix, 0, 1);
+        sc[i] = make_schedule(states[i]->npix, 0, 1, states[i]->min_ppt);
         if (events[i].n > 0)
             kmax = std::max(kmax, sc[i].ntiles);
     }
@@ -634,7 +644,7 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         const int64_t n = (int64_t)events[i].n;
         const int share =
             n > 0 ? std::max(1, (int)((double)slots * (double)n / (double)n_all)) : 1;
-        sc[i] = make_schedule(st->npix, n, share);
+        sc[i] = make_schedule(st->npix, n, share, st->min_ppt);
         BatchItem& x = it[i];
         x = BatchItem{};
         x.ev = EventsDev{events[i].x, events[i].y, events[i].t, events[i].p, n};

@@ -125,3 +125,27 @@ def test_batch_rejects_duplicates_and_overflow(esi):
     batch.close()
     for s in (a, b, c):
         s.close()
+
+
+@pytest.mark.parametrize("W,H", [(640, 480), (333, 7)])
+def test_tile_size_does_not_change_results(esi, W, H):
+    """Every integration tile size (esi_set_tile_pixels) gives the same state
+    and frames, bit for bit."""
+    import torch
+    s = evgen.random_stream(seed=77, width=W, height=H, n=200_000, t_max=300_000,
+                            burst_frac=0.1)
+    tf = np.arange(1, 31, dtype=np.int64) * 10_000
+    ref = None
+    for tile in (0, 256, 512, 1024, 2048):
+        st = esi.State(W, H, C=0.2, k_per_us=3e-6, b=2.0, s_min=-1.0, s_max=1.0)
+        st.set_tile_pixels(tile)
+        fr, _ = st.integrate(s.x, s.y, s.t, s.p, t_frames=tf)
+        out = [a.clone() for a in st.read_state()] + [fr.clone()]
+        torch.cuda.synchronize()
+        st.close()
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(out, ref):
+                assert torch.equal(a, b), tile
+    assert esi.esi_set_tile_pixels(None, 256) == esi.ESI_ERR_INVALID_ARG

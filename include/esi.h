@@ -180,10 +180,11 @@ esi_status esi_get_diagnostics(esi_state *st, esi_diag *out);
 /* Tile size of the integration kernels for later calls on this state: 256,
  * 512, 1024 or 2048 pixels (the smallest allowed: a sensor whose tiles would
  * be more than 2000 gets the next larger size), or 0 for the default (the
- * smallest size with at most 2000 tiles).  Results do not depend on it; for
- * calls with few events per tile larger tiles shorten the per-tile chains of
- * dependent memory accesses, for event-dense calls smaller tiles give more
- * workgroups (an autotuner picks it per workload). */
+ * smallest size with at most 2000 tiles).  N, P and T do not depend on it, S
+ * and frames only to rounding (decay bases are taken per chunk of a tile's
+ * events); for calls with few events per tile larger tiles shorten the
+ * per-tile chains of dependent memory accesses, for event-dense calls
+ * smaller tiles give more workgroups (an autotuner picks it per workload). */
 esi_status esi_set_tile_pixels(esi_state *st, int32_t tile_pixels);
 
 /* Sensor size of a state. */

@@ -1,9 +1,9 @@
 """Tile-size autotuner for batched calls.
 
-The integration tile size (256 to 2048 pixels) changes nothing in the
-results, only the time: event-dense calls want many small tiles (more
-workgroups), calls with few events per tile want large ones (fewer chains of
-dependent memory accesses per call).  ``tune_tiles`` times batched calls on
+The integration tile size (256 to 2048 pixels) changes the results only to
+rounding (N, P, T not at all), and the time: event-dense calls want many
+small tiles (more workgroups), calls with few events per tile want large
+ones (fewer chains of dependent memory accesses per call).  ``tune_tiles`` times batched calls on
 throwaway states of the same sizes and parameters, over sample windows, and
 picks a size per sensor size, one size class at a time (coordinate descent:
 the other classes keep their current choice).  Results are cached per

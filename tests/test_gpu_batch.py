@@ -128,24 +128,24 @@ def test_batch_rejects_duplicates_and_overflow(esi):
 
 
 @pytest.mark.parametrize("W,H", [(640, 480), (333, 7)])
-def test_tile_size_does_not_change_results(esi, W, H):
-    """Every integration tile size (esi_set_tile_pixels) gives the same state
-    and frames, bit for bit."""
+def test_tile_size_keeps_results(esi, W, H):
+    """Every integration tile size (esi_set_tile_pixels) gives the same N, P,
+    T exactly and S and frames within the parity tolerance of the oracle (the
+    decay bases are taken relative to each chunk's first event, so the
+    rounding depends on the chunking)."""
     import torch
+    prm = dict(C=0.2, k_per_us=3e-6, b=2.0, s_min=-1.0, s_max=1.0)
     s = evgen.random_stream(seed=77, width=W, height=H, n=200_000, t_max=300_000,
                             burst_frac=0.1)
     tf = np.arange(1, 31, dtype=np.int64) * 10_000
-    ref = None
+    fo, o = oracle_run(s, prm, t_frames=tf)
     for tile in (0, 256, 512, 1024, 2048):
-        st = esi.State(W, H, C=0.2, k_per_us=3e-6, b=2.0, s_min=-1.0, s_max=1.0)
+        st = esi.State(W, H, **prm)
         st.set_tile_pixels(tile)
         fr, _ = st.integrate(s.x, s.y, s.t, s.p, t_frames=tf)
-        out = [a.clone() for a in st.read_state()] + [fr.clone()]
-        torch.cuda.synchronize()
+        S, T, N, P = (a.cpu().numpy() for a in st.read_state())
+        assert_state((S, T, N.view(np.uint32), P), o, prm["C"], f"tile {tile}")
+        assert_frames(fr.cpu().numpy(), fo, prm, f"tile {tile}")
         st.close()
-        if ref is None:
-            ref = out
-        else:
-            for a, b in zip(out, ref):
-                assert torch.equal(a, b), tile
     assert esi.esi_set_tile_pixels(None, 256) == esi.ESI_ERR_INVALID_ARG
+    assert esi.esi_set_tile_pixels(None, 300) == esi.ESI_ERR_INVALID_ARG

@@ -244,6 +244,73 @@ def preset_batch(name: str = "c4", duration_us: int = 200_000, n_streams: int = 
 
 
 # ---------------------------------------------------------------------------
+# The paper's qualitative scenes (Sec. III-A, Fig. 2; Sec. III-B, Fig. 4)
+# ---------------------------------------------------------------------------
+
+def moving_circle(width: int = 200, height: int = 120, radius: float = 20.0,
+                  x0: float = 140.0, speed_px_s: float = 400.0, t_start_us: int = 100_000,
+                  duration_us: int = 400_000, reflectivity: float = 0.3,
+                  C: float = 0.2) -> Stream:
+    """Fig. 2's simulation: intensity rising linearly along x, a disc of the
+    given reflectivity starting at (x0, height / 2), still until t_start, then
+    moving along -x.  The ramp is static, so only the disc's edge emits
+    events: a pixel the disc enters sees its log intensity drop by
+    log(1 / reflectivity), i.e. floor(that / C) negative events at the entry
+    time (floored to us), and as many positive events when the disc leaves
+    it.  Pixels inside the disc at the start only see it leave (the ghost of
+    the initial position)."""
+    steps = int(np.floor(np.log(1.0 / reflectivity) / C + 1e-9))
+    yc = height / 2.0
+    xs, ys, ts, ps = [], [], [], []
+    for y in range(height):
+        dy = y + 0.5 - yc
+        if abs(dy) >= radius:
+            continue
+        h = np.sqrt(radius * radius - dy * dy)
+        for x in range(width):
+            cx = x + 0.5
+            t_in = t_start_us + (x0 - cx - h) / speed_px_s * 1e6
+            t_out = t_start_us + (x0 - cx + h) / speed_px_s * 1e6
+            if t_in > t_start_us and t_in < duration_us:
+                for _ in range(steps):
+                    xs.append(x), ys.append(y), ts.append(int(t_in)), ps.append(-1)
+            if t_out > t_start_us and t_out < duration_us:
+                for _ in range(steps):
+                    xs.append(x), ys.append(y), ts.append(int(t_out)), ps.append(1)
+    order = np.argsort(np.array(ts, np.int64), kind="stable")
+    return Stream(np.array(xs, np.uint16)[order], np.array(ys, np.uint16)[order],
+                  np.array(ts, np.int64)[order], np.array(ps, np.int8)[order],
+                  width, height, duration_us,
+                  meta={"scene": "moving_circle", "steps": steps, "radius": radius, "x0": x0,
+                        "speed_px_s": speed_px_s, "t_start_us": t_start_us})
+
+
+def noise_only(seed: int = 6, width: int = 346, height: int = 260, rate_hz_px: float = 2.0,
+               duration_us: int = 2_000_000, hot_pixels: int = 3,
+               hot_rate_hz: float = 2000.0) -> Stream:
+    """Fig. 4's setting without the thrown object: a static scene, so every
+    event is noise.  Per-pixel Poisson noise of random polarity at
+    rate_hz_px, plus a few hot pixels firing at hot_rate_hz with random
+    polarity; the intensity at the end equals the one at the start."""
+    rng = np.random.default_rng(seed)
+    npix = width * height
+    n = rng.poisson(rate_hz_px * npix * duration_us * 1e-6)
+    q = rng.integers(0, npix, n)
+    t = rng.integers(0, duration_us, n)
+    hq = rng.choice(npix, hot_pixels, replace=False)
+    nh = int(hot_rate_hz * duration_us * 1e-6)
+    q = np.concatenate([q, np.repeat(hq, nh)])
+    t = np.concatenate([t, np.tile(np.linspace(0, duration_us - 1, nh).astype(np.int64),
+                                   hot_pixels)])
+    p = rng.choice(np.array([-1, 1], np.int8), q.size)
+    order = np.argsort(t, kind="stable")
+    q, t, p = q[order], t[order], p[order]
+    return Stream((q % width).astype(np.uint16), (q // width).astype(np.uint16),
+                  t.astype(np.int64), p, width, height, duration_us,
+                  meta={"scene": "noise_only", "hot": hq.tolist()})
+
+
+# ---------------------------------------------------------------------------
 # Small adversarial streams for tests (numpy, seeded)
 # ---------------------------------------------------------------------------
 

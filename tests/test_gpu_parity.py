@@ -365,3 +365,20 @@ def test_u8_only_frames(esi):
         assert_u8(u_only.cpu().numpy(), fo, prm, "u8-only")
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("scene,k", [("fig2", 0.0), ("fig2", 1.0 / 120_000),
+                                     ("fig4", 0.0), ("fig4", 1e-5)])
+def test_paper_scenes(esi, scene, k):
+    """The paper's illustrative scenes (the moving disc of Fig. 2, the
+    noise-only accumulation of Fig. 4; their qualitative claims are checked
+    on the oracle in test_scenes.py) on the GPU path, state and frames."""
+    if scene == "fig2":
+        s = evgen.moving_circle()
+        prm = dict(C=0.2, k_per_us=k, b=2.0, s_min=-10.0, s_max=10.0)
+        tf = np.array([50_000, 200_000, 320_001, 350_000], np.int64)
+    else:
+        s = evgen.noise_only()
+        prm = dict(C=0.2, k_per_us=k, b=2.0, s_min=-1e6, s_max=1e6)
+        tf = np.array([1_000_000, 1_999_999], np.int64)
+    _check(esi, s, prm, tf, where=f"{scene} k={k}")

@@ -59,6 +59,9 @@ class Server:
         self.copy = torch.cuda.Stream(self.dev)   # default priority
         self.inflight = collections.deque()  # (event, [(sid, packet id, arrival)])
         self.retiring = collections.deque()  # (event, session) closed, not freed yet
+        # states of closed sessions kept for reuse (same size and parameters):
+        # creating and destroying states synchronises the device
+        self.pool = collections.defaultdict(list)
         self.done = []                       # (sid, packet id, latency s)
         self._bufs = [None, None]
         self._flip = 0
@@ -71,16 +74,40 @@ class Server:
         """Register a session; True if admitted now, False if it waits."""
         s = Session(sid, int(width), int(height), params, self._cost(width, height))
         self.sessions[sid] = s
-        if self.used + s.cost <= self.budget:
+        if not self.waiting and self._fits(s):
             self._admit(s)
             return True
         self.waiting.append(s)
         return False
 
+    @staticmethod
+    def _key(s):
+        return (s.width, s.height, tuple(sorted(s.params.items())))
+
     def _admit(self, s):
+        pooled = self.pool.get(self._key(s))
+        if pooled:
+            # a pooled state already counts in `used`; reset it in stream order
+            s.state, s.frame = pooled.pop()
+            s.state.reset()
+            return
         s.state = State(s.width, s.height, **s.params)
         s.frame = torch.empty((1, s.height, s.width), dtype=torch.float32, device=self.dev)
         self.used += s.cost
+
+    def _fits(self, s) -> bool:
+        """Room for s: a pooled state of its kind, free budget, or budget
+        freed by destroying pooled states of other kinds."""
+        if self.pool.get(self._key(s)):
+            return True
+        while self.used + s.cost > self.budget:
+            victim = next((k for k, v in self.pool.items() if v), None)
+            if victim is None:
+                return False
+            st, _ = self.pool[victim].pop()
+            st.close()
+            self.used -= self._cost(victim[0], victim[1])
+        return True
 
     def close(self, sid):
         """Retire a session.  Its memory is freed, and its budget handed to
@@ -98,11 +125,10 @@ class Server:
     def _reap(self):
         while self.retiring and self.retiring[0][0].query():
             _, s = self.retiring.popleft()
-            s.state.close()
+            self.pool[self._key(s)].append((s.state, s.frame))
             s.state = None
             s.frame = None
-            self.used -= s.cost
-        while self.waiting and self.used + self.waiting[0].cost <= self.budget:
+        while self.waiting and self._fits(self.waiting[0]):
             self._admit(self.waiting.popleft())
 
     def admitted(self, sid) -> bool:
@@ -213,4 +239,9 @@ class Server:
             self.close(sid)
         self.compute.synchronize()
         self._reap()
+        for v in self.pool.values():
+            for st, _ in v:
+                st.close()
+        self.pool.clear()
+        self.used = 0
         self.batch.close()

@@ -89,3 +89,55 @@ def test_served_equals_alone(esi):
             assert torch.equal(a, b), i
         assert torch.equal(got_frame, fr), i
         alone.close()
+
+
+def test_served_reuses_pooled_states(esi):
+    """Sessions of one size and parameters under a budget for two: later
+    sessions run on the reset states of closed ones and still end as if
+    integrated alone."""
+    import torch
+    from paper_2508_02238_amd.serve import Server
+    prm = dict(C=0.25, k_per_us=1e-5, b=1.0, s_min=-1.0, s_max=1.0, flags=1)
+    W, H = 64, 48
+    streams = [_stream(20 + i, W, H) for i in range(6)]
+    probe = Server(budget_bytes=1 << 40, max_batch=2, max_packet_events=1 << 14)
+    cost = probe._cost(W, H)
+    probe.close_all()
+    srv = Server(budget_bytes=2 * cost, max_batch=8, max_packet_events=1 << 14)
+    got = {}
+    for i in range(6):
+        srv.open(i, W, H, **prm)
+    done_sessions = 0
+    sent = [0] * 6
+    while done_sessions < 6:
+        for i in range(6):
+            if i in got or not srv.admitted(i):
+                continue
+            if sent[i] < PACKETS and not srv.sessions[i].pending:
+                ws, tf = _packet(streams[i], sent[i])
+                srv.submit(i, ws.x, ws.y, ws.t, ws.p, tf, pid=sent[i])
+                sent[i] += 1
+        srv.tick()
+        srv.poll()
+        for i in range(6):
+            if i in got or not srv.admitted(i) or sent[i] < PACKETS or srv.sessions[i].pending:
+                continue
+            srv.poll(wait=True)
+            got[i] = ([a.clone() for a in srv.sessions[i].state.read_state()],
+                      srv.sessions[i].frame.clone())
+            torch.cuda.synchronize()
+            srv.close(i)
+            done_sessions += 1
+    assert sum(len(v) for v in srv.pool.values()) >= 1
+    srv.close_all()
+    for i in range(6):
+        alone = esi.State(W, H, **prm)
+        for k in range(PACKETS):
+            ws, tf = _packet(streams[i], k)
+            fr, _ = alone.integrate(ws.x, ws.y, ws.t, ws.p, t_frames=np.array([tf], np.int64))
+        ref = alone.read_state()
+        torch.cuda.synchronize()
+        for a, b in zip(got[i][0], ref):
+            assert torch.equal(a, b), i
+        assert torch.equal(got[i][1], fr), i
+        alone.close()

@@ -227,7 +227,9 @@ esi_status esi_batch_destroy(esi_batch *batch);
  * errors return ESI_ERR_INVALID_ARG before anything is enqueued; a poisoned
  * state returns ESI_ERR_POISONED; a HIP failure poisons every state of the
  * call.  The call may wait for the previous call's descriptor copy (host
- * side) and for the stream when a state's scratch must grow. */
+ * side) and for the stream when a state's scratch must grow; its descriptor
+ * copy waits (on the device) for the previous call's kernels, so successive
+ * calls on one batch object may use different streams. */
 esi_status esi_integrate_batch(esi_batch *batch, int32_t n_items, esi_state *const *states,
                                const esi_events *events, const int64_t *const *t_frames,
                                const int32_t *n_frames, float *const *frames,

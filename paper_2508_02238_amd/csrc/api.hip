@@ -45,6 +45,7 @@ struct esi_batch {
     void* host = nullptr;
     void* dev = nullptr;
     hipEvent_t copied = nullptr;  // recorded after the last staging copy
+    hipEvent_t used = nullptr;    // recorded after the last call's kernels
     bool pending = false;
 };
 
@@ -535,6 +536,8 @@ void batch_free(esi_batch* b)
 {
     if (b->copied)
         (void)hipEventDestroy(b->copied);
+    if (b->used)
+        (void)hipEventDestroy(b->used);
     if (b->dev)
         (void)hipFree(b->dev);
     if (b->host)
@@ -570,6 +573,11 @@ esi_status esi_batch_create(int32_t max_items, esi_batch** out)
     }
     if (hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
         b->copied = nullptr;
+        batch_free(b);
+        return ESI_ERR_HIP;
+    }
+    if (hipEventCreateWithFlags(&b->used, hipEventDisableTiming) != hipSuccess) {
+        b->used = nullptr;
         batch_free(b);
         return ESI_ERR_HIP;
     }
@@ -678,9 +686,9 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cls[a] < cls[c]; });
 
     // the previous call's staging copy must have been read before reuse
-    if (b->pending && hipEventSynchronize(b->copied) != hipSuccess)
+    const bool earlier = b->pending;
+    if (earlier && hipEventSynchronize(b->copied) != hipSuccess)
         return ESI_ERR_HIP;
-    b->pending = false;
     char* h = (char*)b->host;
     BatchItem* hi = (BatchItem*)h;
     uint32_t* ub = (uint32_t*)(h + batch_items_bytes(b->max_items));
@@ -706,7 +714,10 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
             states[i]->poisoned = true;
         return ESI_ERR_HIP;
     };
-    if (hipMemcpyAsync(b->dev, b->host, b->bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+    // the previous call's kernels (possibly on another stream) read the
+    // device descriptors until they finish
+    if ((earlier && hipStreamWaitEvent(stream, b->used, 0) != hipSuccess) ||
+        hipMemcpyAsync(b->dev, b->host, b->bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipEventRecord(b->copied, stream) != hipSuccess)
         return fail();
     b->pending = true;
@@ -722,6 +733,8 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
             return fail();
         k0 = k1;
     }
+    if (hipEventRecord(b->used, stream) != hipSuccess)
+        return fail();
     for (int32_t i = 0; i < n_items; ++i)
         states[i]->calls++;
     return ESI_OK;

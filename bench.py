@@ -73,6 +73,8 @@ def main() -> int:
     ap.add_argument("--fps", type=float, default=100.0)
     ap.add_argument("--u8", action="store_true", help="also write 8-bit frames")
     ap.add_argument("--u8-only", action="store_true", help="write 8-bit frames only")
+    ap.add_argument("--tile-pixels", type=int, default=0,
+                    help="integration tile size (256-2048; 0: the library's default)")
     ap.add_argument("--flags", type=int, default=0,
                     help="method flags: 1 decay then add, 2 lazy (undecayed) snapshots")
     ap.add_argument("--cpu-sample-s", type=float, default=0.0,
@@ -126,6 +128,8 @@ def main() -> int:
     frames = torch.empty((nf, H, W), dtype=torch.float32, device=dev) if want_f32 else None
     frames_u8 = torch.empty((nf, H, W), dtype=torch.uint8, device=dev) if want_u8 else None
     st = esi.State(W, H, **prm)
+    if args.tile_pixels:
+        st.set_tile_pixels(args.tile_pixels)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
     def step():

@@ -151,6 +151,12 @@ class Server:
         k = self._flip
         self._flip ^= 1
         b = self._bufs[k]
+        if b is not None and b["ready"] is not None:
+            # its last tick has consumed it; wait before reuse, and before a
+            # larger buffer replaces it (its freed device memory may go to
+            # the new buffer, which the copy stream writes)
+            b["ready"].synchronize()
+            b["ready"] = None
         if b is None or b["cap"] < n:
             cap = max(n, 1 << 16) * 5 // 4
             b = {"cap": cap,
@@ -162,8 +168,9 @@ class Server:
                  "tfd": torch.empty(self.max_batch, dtype=torch.int64, device=self.dev),
                  "ready": None}
             self._bufs[k] = b
-        if b["ready"] is not None:          # its last tick has consumed it
-            b["ready"].synchronize()
+            # the new device memory comes from the compute stream's pool: the
+            # copy stream writes it only after the compute stream's earlier work
+            self.copy.wait_stream(self.compute)
         return b
 
     def tick(self) -> int:

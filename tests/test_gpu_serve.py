@@ -141,3 +141,47 @@ def test_served_reuses_pooled_states(esi):
             assert torch.equal(a, b), i
         assert torch.equal(got[i][1], fr), i
         alone.close()
+
+
+def test_served_growing_packets(esi):
+    """Packets that grow from tick to tick, so the server's staging buffers
+    are replaced while earlier ticks may still run: every session still ends
+    as if integrated alone."""
+    import torch
+    from paper_2508_02238_amd.serve import Server
+    prm = dict(C=0.2, k_per_us=2e-5, b=2.0, s_min=-1.0, s_max=1.0)
+    W, H = 346, 260
+    sizes = [1_000, 8_000, 30_000, 60_000, 2_000, 45_000]
+    n_sess = 3
+    packets = [[evgen.random_stream(seed=700 + 10 * i + k, width=W, height=H, n=n,
+                                    t_min=k * PACKET_US, t_max=(k + 1) * PACKET_US,
+                                    burst_frac=0.05)
+                for k, n in enumerate(sizes)] for i in range(n_sess)]
+    srv = Server(budget_bytes=1 << 34, max_batch=8, max_packet_events=1 << 17)
+    for i in range(n_sess):
+        assert srv.open(i, W, H, **prm)
+    for k in range(len(sizes)):
+        for i in range(n_sess):
+            s = packets[i][k]
+            srv.submit(i, s.x, s.y, s.t, s.p, (k + 1) * PACKET_US - 1, pid=k)
+        assert srv.tick() == n_sess
+        srv.poll()                      # no wait: ticks stay in flight
+    srv.poll(wait=True)
+    got = [([a.clone() for a in srv.sessions[i].state.read_state()],
+            srv.sessions[i].frame.clone()) for i in range(n_sess)]
+    torch.cuda.synchronize()
+    assert len(srv.done) == n_sess * len(sizes)
+    srv.close_all()
+    for i in range(n_sess):
+        alone = esi.State(W, H, **prm)
+        fr = None
+        for k in range(len(sizes)):
+            s = packets[i][k]
+            fr, _ = alone.integrate(s.x, s.y, s.t, s.p,
+                                    t_frames=np.array([(k + 1) * PACKET_US - 1], np.int64))
+        ref = alone.read_state()
+        torch.cuda.synchronize()
+        for a, b in zip(got[i][0], ref):
+            assert torch.equal(a, b), i
+        assert torch.equal(got[i][1], fr), i
+        alone.close()

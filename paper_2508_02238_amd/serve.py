@@ -85,14 +85,16 @@ class Server:
         return (s.width, s.height, tuple(sorted(s.params.items())))
 
     def _admit(self, s):
-        pooled = self.pool.get(self._key(s))
-        if pooled:
-            # a pooled state already counts in `used`; reset it in stream order
-            s.state, s.frame = pooled.pop()
-            s.state.reset()
-            return
-        s.state = State(s.width, s.height, **s.params)
-        s.frame = torch.empty((1, s.height, s.width), dtype=torch.float32, device=self.dev)
+        # state set-up runs on the compute stream, in order with the ticks
+        with torch.cuda.stream(self.compute):
+            pooled = self.pool.get(self._key(s))
+            if pooled:
+                # a pooled state already counts in `used`; reset it in stream order
+                s.state, s.frame = pooled.pop()
+                s.state.reset()
+                return
+            s.state = State(s.width, s.height, **s.params)
+            s.frame = torch.empty((1, s.height, s.width), dtype=torch.float32, device=self.dev)
         self.used += s.cost
 
     def _fits(self, s) -> bool:

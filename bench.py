@@ -184,7 +184,8 @@ def main() -> int:
         "unit": "GB/s",
         "frac": round(alg / (integ_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "traffic": (measured_traffic(args.workload, args.fps)
-                    if (want_f32 and not want_u8 and args.flags == 0) else None),
+                    if (want_f32 and not want_u8 and args.flags == 0 and not args.tile_pixels)
+                    else None),
         "algorithmic_bytes": alg,
         "avg_launch_ms": round(integ_avg_ms, 4),
     }

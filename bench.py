@@ -7,14 +7,16 @@ event stream (Alg. 2 event loop with the clamp of Eq. (13)) and writes all
 of its frames (Eq. (14), decayed snapshots, FP32).  Inputs are resident in
 HBM before timing starts.
 
-Default workload (c2): 640x480 sensor, 10 s of a seeded random-walk
-translating texture, about 20M events, frames at 100 FPS (1000 frames).
+Default workload (c3, the largest single-stream one): 1280x720 sensor, 5 s
+of a seeded rotating radial-spoke pattern at 20 rev/s, about 153M events,
+frames at 100 FPS (500 frames).
 
 Prints one JSON line on stdout: Gevents/s integrated (value), frames/s,
-the roofline of the dominant kernel (integration, measured with HIP events
-recorded by the library on its stream), the whole-step roofline, the parity
-of this run's output against the FP64 oracle, and the oracle itself timed on
-the host as a CPU baseline.
+the roofline of the call (its algorithmic bytes over the GPU time of the
+call, measured with HIP events the library records on its stream, with the
+bucketing and integration kernels also reported on their own bytes), the
+parity of this run's output against the FP64 oracle, and the oracle itself
+timed on the host, on one core and on every core, as a CPU baseline.
 """
 from __future__ import annotations
 
@@ -43,25 +45,63 @@ def algorithmic_bytes(n: int, npix: int, nf: int, u8: bool, f32: bool = True) ->
 
 
 def measured_traffic(workload: str, fps: float):
-    """HBM bytes per launch of the integration kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
-    reading of a plain copy of known size), or None when no summary exists for
-    this workload or the kernel's sources changed since it was taken."""
+    """HBM bytes per call of the call's kernels (bucketing and integration)
+    from the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
+    each scaled by the reading of a plain copy of known size), or None when
+    no summary exists for this workload or the kernel sources changed since
+    it was taken.  Returns (total, {kernel group: bytes})."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_integrate_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{fps:g}fps.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if float(rec.get("fps", 100.0)) != fps:
-        return None
     h = hashlib.sha256()
     for src in rec["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
     if h.hexdigest()[:16] != rec["sources_sha256_16"]:
         return None
-    return int(rec["read_bytes"]) + int(rec["write_bytes"])
+    groups = {g: int(v["read_bytes"]) + int(v["write_bytes"]) for g, v in rec["groups"].items()}
+    return sum(groups.values()), groups
+
+
+def cpu_baseline(s, tf, prm, sample_s: float, min_s: float, threads: int):
+    """The oracle timed on the host over a bounded sample of the workload (its
+    first `sample_s` seconds of events and the frames in them): whole passes
+    from a fresh state until about min_s seconds, on one core (the serial
+    loop) and on `threads` cores (one band of rows per thread, every thread
+    scanning all events)."""
+    import numpy as np
+
+    import oracle
+    m = int(np.searchsorted(s.t, int(sample_s * 1e6), side="left"))
+    tf_s = tf[tf <= int(sample_s * 1e6)]
+    W, H = s.width, s.height
+
+    def timed(run):
+        el, reps = 0.0, 0
+        while reps == 0 or (el < min_s and reps < 16):
+            o = oracle.State(W, H, oracle.Params(**prm))
+            h0 = time.perf_counter()
+            run(o)
+            el += time.perf_counter() - h0
+            reps += 1
+        return el, reps
+
+    el1, r1 = timed(lambda o: o.integrate(s.x[:m], s.y[:m], s.t[:m], s.p[:m], t_frames=tf_s))
+    elN, rN = timed(lambda o: o.integrate_rows(s.x[:m], s.y[:m], s.t[:m], s.p[:m],
+                                                t_frames=tf_s, threads=threads))
+    return {"value": round(r1 * m / el1 / 1e9, 6), "unit": "Gevents/s", "cores": 1,
+            "kind": "oracle",
+            "frames_per_s": round(r1 * len(tf_s) / el1, 2),
+            "all_cores": {"value": round(rN * m / elN / 1e9, 6), "unit": "Gevents/s",
+                          "cores": threads, "frames_per_s": round(rN * len(tf_s) / elN, 2),
+                          "method": "one band of rows per thread, each scanning all events",
+                          "seconds": round(elN, 2), "passes": rN},
+            "sample": (f"the first {sample_s:g} s of the workload ({m} events, {len(tf_s)} "
+                       f"frames), serial FP64 oracle, {r1} pass(es) in {el1:.1f} s on one core"),
+            "cpu_model": _cpu_model()}
 
 
 def main() -> int:
@@ -69,18 +109,24 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c3",
+                    choices=["c1", "c2", "c3", "c3hot", "c4", "c5"])
     ap.add_argument("--fps", type=float, default=100.0)
     ap.add_argument("--u8", action="store_true", help="also write 8-bit frames")
     ap.add_argument("--u8-only", action="store_true", help="write 8-bit frames only")
     ap.add_argument("--tile-pixels", type=int, default=0,
                     help="integration tile size (256-2048; 0: the library's default)")
     ap.add_argument("--flags", type=int, default=0,
-                    help="method flags: 1 decay then add, 2 lazy (undecayed) snapshots")
+                    help="method flags: 1 decay then add, 2 lazy (undecayed) snapshots, "
+                         "4 exponential decay")
     ap.add_argument("--cpu-sample-s", type=float, default=0.0,
-                    help="seconds of the workload the CPU oracle is timed on (0: all of it)")
-    ap.add_argument("--cpu-min-s", type=float, default=10.0,
-                    help="repeat the CPU oracle pass over the sample until this many seconds")
+                    help="seconds of the workload the CPU oracle is timed on (0: a sample "
+                         "of about 15M events)")
+    ap.add_argument("--cpu-min-s", type=float, default=8.0,
+                    help="repeat each CPU oracle pass over the sample until this many seconds")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the all-core CPU baseline (0: the host's share, "
+                         "at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -108,6 +154,7 @@ def main() -> int:
     if args.workload == "c5":
         return bench_served(args)
     t0 = time.time()
+    log(f"[bench] generating workload {args.workload}")
     s = evgen.preset(args.workload)
     tf = s.frame_times(args.fps)
     n, W, H, nf = s.n, s.width, s.height, len(tf)
@@ -162,8 +209,10 @@ def main() -> int:
     assert rc == esi.ESI_OK and calls == args.steps
     esi.esi_profile_enable(st.handle, False)
     ms_per_step = gpu_ms / args.steps
+    bucket_avg, integ_avg = bucket_ms / calls, integ_ms / calls
+    call_ms = bucket_avg + integ_avg
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (host {host_ms / args.steps:.3f}), "
-        f"bucketing {bucket_ms / calls:.3f} ms, integration {integ_ms / calls:.3f} ms")
+        f"call {call_ms:.3f} ms = bucketing {bucket_avg:.3f} + integration {integ_avg:.3f}")
 
     if args.copy_probe_mb:
         a = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device=dev)
@@ -174,26 +223,38 @@ def main() -> int:
         log(f"[bench] copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
         del a, b
 
+    # algorithmic bytes: the whole call, and each phase on the bytes it must
+    # move itself (bucketing: the events; integration: state and frames)
     alg = algorithmic_bytes(n, npix, nf, want_u8, want_f32)
-    integ_avg_ms = integ_ms / calls
+    alg_bucket = 13 * n
+    alg_integ = alg - alg_bucket
+    gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
+    default_form = want_f32 and not want_u8 and args.flags == 0 and not args.tile_pixels
+    meas = measured_traffic(args.workload, args.fps) if default_form else None
     roofline = {
-        "kernel": "k_integrate (per-tile event loop + frames)",
+        "scope": "one esi_integrate_window call: bucketing (k_hist, k_seg_sum, k_seg_down, "
+                 "k_bucket) and integration (k_integrate), timed with HIP events the "
+                 "library records on its stream",
         "bound": "hbm",
-        "achieved": round(alg / (integ_avg_ms * 1e-3) / 1e9, 1),
+        "achieved": round(gbs(alg, call_ms), 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": round(alg / (integ_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "traffic": (measured_traffic(args.workload, args.fps)
-                    if (want_f32 and not want_u8 and args.flags == 0 and not args.tile_pixels)
-                    else None),
+        "frac": round(gbs(alg, call_ms) / HBM_PEAK_GBS, 4),
+        "traffic": meas[0] if meas else None,
         "algorithmic_bytes": alg,
-        "avg_launch_ms": round(integ_avg_ms, 4),
-    }
-    roofline_path = {
-        "achieved": round(alg / (ms_per_step * 1e-3) / 1e9, 1),
-        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "bucketing_ms": round(bucket_ms / calls, 4),
+        "call_ms": round(call_ms, 4),
+        "kernels": {
+            "bucketing": {"kernels": "k_hist, k_seg_sum, k_seg_down, k_bucket",
+                          "algorithmic_bytes": alg_bucket, "avg_ms": round(bucket_avg, 4),
+                          "achieved": round(gbs(alg_bucket, bucket_avg), 1),
+                          "frac": round(gbs(alg_bucket, bucket_avg) / HBM_PEAK_GBS, 4),
+                          "traffic": meas[1].get("bucketing") if meas else None},
+            "integration": {"kernels": "k_integrate",
+                            "algorithmic_bytes": alg_integ, "avg_ms": round(integ_avg, 4),
+                            "achieved": round(gbs(alg_integ, integ_avg), 1),
+                            "frac": round(gbs(alg_integ, integ_avg) / HBM_PEAK_GBS, 4),
+                            "traffic": meas[1].get("integration") if meas else None},
+        },
     }
 
     parity = None
@@ -202,6 +263,7 @@ def main() -> int:
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         from esi_parity import REL, u8_codes
         sel = sorted(set([0, nf // 3, nf // 2, nf - 1]))
+        log(f"[bench] parity: oracle over the whole workload, frames {sel}")
         h0 = time.time()
         o = oracle.State(W, H, oracle.Params(**prm))
         fo = o.integrate(s.x, s.y, s.t, s.p, t_frames=tf, frame_sel=sel)
@@ -216,37 +278,23 @@ def main() -> int:
         if frames_u8 is not None:
             ug = frames_u8[sel].cpu().numpy()
             u8_max = int(np.abs(ug.astype(np.int32) - u8_codes(fo).astype(np.int32)).max())
-        ok = (np.array_equal(N.view(np.uint32), o.N) and np.array_equal(P, o.P)
-              and np.array_equal(T, o.T) and s_err.max() <= REL and f_max <= REL
-              and u8_max <= 1)
+        exact = (np.array_equal(N.view(np.uint32), o.N) and np.array_equal(P, o.P)
+                 and np.array_equal(T, o.T))
+        ok = exact and s_err.max() <= REL and f_max <= REL and u8_max <= 1
         parity = {"ok": bool(ok), "max_rel_S": float(s_err.max()),
                   "max_rel_frame": f_max, "max_u8_code_diff": u8_max, "frames_checked": sel,
-                  "exact_N_P_T": bool(np.array_equal(N.view(np.uint32), o.N)
-                                      and np.array_equal(P, o.P) and np.array_equal(T, o.T))}
+                  "exact_N_P_T": bool(exact)}
         log(f"[bench] parity vs oracle: {parity} ({time.time() - h0:.1f} s)")
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        span_s = args.cpu_sample_s if args.cpu_sample_s > 0 else s.duration_us / 1e6
-        m = int(np.searchsorted(s.t, int(span_s * 1e6), side="left"))
-        tf_s = tf[tf <= int(span_s * 1e6)]
-        # whole passes over the sample, each from a fresh state, until about
-        # --cpu-min-s seconds of oracle time have been spent
-        el, reps = 0.0, 0
-        while reps == 0 or (el < args.cpu_min_s and reps < 16):
-            o = oracle.State(W, H, oracle.Params(**prm))
-            h0 = time.perf_counter()
-            o.integrate(s.x[:m], s.y[:m], s.t[:m], s.p[:m], t_frames=tf_s)
-            el += time.perf_counter() - h0
-            reps += 1
-        cpu = {"value": round(reps * m / el / 1e9, 6), "unit": "Gevents/s", "cores": 1,
-               "kind": "oracle",
-               "frames_per_s": round(reps * len(tf_s) / el, 2),
-               "sample": (f"{reps} pass(es) over the first {span_s:g} s of the workload "
-                          f"({m} events and {len(tf_s)} frames each), serial FP64 "
-                          f"oracle, {el:.1f} s in all"),
-               "cpu_model": _cpu_model()}
+        span_s = args.cpu_sample_s
+        if span_s <= 0:
+            # about 15M events (c1 and c2 whole; c3 its first half second)
+            span_s = min(s.duration_us / 1e6, 15e6 / max(n / (s.duration_us / 1e6), 1.0))
+        threads = args.cpu_threads or max(1, min(os.cpu_count() or 1, 16))
+        log(f"[bench] cpu baseline: first {span_s:g} s, 1 and {threads} threads")
+        cpu = cpu_baseline(s, tf, prm, span_s, args.cpu_min_s, threads)
         log(f"[bench] cpu baseline: {cpu}")
 
     value = n / (ms_per_step * 1e-3) / 1e9
@@ -273,7 +321,6 @@ def main() -> int:
                    "params": prm,
                    "frame_dtype": "u8" if args.u8_only else ("f32+u8" if args.u8 else "f32")},
         "roofline": roofline,
-        "roofline_path": roofline_path,
         "parity": parity,
         "cpu_baseline": cpu,
     }

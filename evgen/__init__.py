@@ -14,6 +14,7 @@ Workloads (sizes, rates, structure):
       [0.15, 0.25], about 18M scene events plus 10% Poisson noise, seed 2.
   c3  1280x720, 5 s, rotating radial spokes (20 rev/s, 4 spokes, 1 px
       edges), C = 0.2, about 150M events, seed 3.
+  c3hot  c3 plus hot pixels: 0.01% of pixels firing at 10-100 kHz.
 Frame times: every 10 ms (100 FPS) or 1 ms (1000 FPS), t_f = (j+1) * period.
 """
 from __future__ import annotations
@@ -52,7 +53,7 @@ class _Cfg(ctypes.Structure):
         ("spoke_rev_s", ctypes.c_double), ("spoke_radius_frac", ctypes.c_double),
         ("spoke_edge_px", ctypes.c_double), ("spoke_count", ctypes.c_int32),
         ("hot_fraction", ctypes.c_double), ("hot_rate_hz", ctypes.c_double),
-        ("tune", ctypes.c_int32),
+        ("hot_rate_hi_hz", ctypes.c_double), ("tune", ctypes.c_int32),
     ]
 
 
@@ -86,6 +87,7 @@ class StreamSpec:
     spoke_count: int = 4
     hot_fraction: float = 0.0
     hot_rate_hz: float = 0.0
+    hot_rate_hi_hz: float = 0.0
     tune: bool = False
 
 
@@ -104,6 +106,11 @@ PRESETS = {
                      seed=3, amplitude=0.16, spoke_radius_frac=349.5185 / 720,
                      target_scene_events=150e6, noise_fraction=0.0),
 }
+# The stress variant of c3 (not a measured configuration of its own): the same
+# stream plus hot pixels, 0.01% of the sensor firing at 10-100 kHz each
+# (log-uniform), which gives runs of 10^4 and more events at one pixel.
+PRESETS["c3hot"] = StreamSpec(**{**PRESETS["c3"].__dict__, "hot_fraction": 1e-4,
+                                 "hot_rate_hz": 10e3, "hot_rate_hi_hz": 100e3})
 
 # Integrator parameters used with these workloads (the paper gives C only).
 DEFAULT_PARAMS = dict(C=0.2, k_per_us=2e-6, b=2.0, s_min=-1.0, s_max=1.0, t0_us=0, flags=0)
@@ -172,7 +179,8 @@ def generate(spec: StreamSpec, threads: int | None = None) -> Stream:
                  "amplitude", "noise_fraction", "step_us", "grating_period_px",
                  "grating_speed_px_s", "tex_speed_px_s", "tex_vel_tau_s",
                  "tex_lambda_lo", "tex_lambda_hi", "spoke_rev_s",
-                 "spoke_radius_frac", "spoke_edge_px", "hot_fraction", "hot_rate_hz"):
+                 "spoke_radius_frac", "spoke_edge_px", "hot_fraction", "hot_rate_hz",
+                 "hot_rate_hi_hz"):
         setattr(c, name, float(getattr(spec, name)))
     c.spoke_count = int(spec.spoke_count)
     c.tune = 1 if spec.tune else 0

@@ -19,7 +19,8 @@
  *              profile with edges e px wide.
  *   3 none     no scene (noise and hot pixels only).
  * Plus per-pixel Poisson noise (uniform in time, random polarity) and
- * optional hot pixels (Poisson at a high rate, 3/4 positive).
+ * optional hot pixels (Poisson at a high rate, 3/4 positive; the rate is one
+ * value, or per pixel log-uniform between two).
  *
  * On request one scene parameter is tuned so that the number of scene events
  * hits a target (bisection on the count over a pixel subsample): the
@@ -53,6 +54,7 @@ typedef struct {
     double spoke_rev_s, spoke_radius_frac, spoke_edge_px;
     int32_t spoke_count;
     double hot_fraction, hot_rate_hz;
+    double hot_rate_hi_hz; /* > hot_rate_hz: each hot pixel's rate log-uniform in between */
     int32_t tune; /* nonzero: tune the scene parameter to target_scene_events */
 } evgen_cfg;
 
@@ -374,7 +376,10 @@ static int pixel_noise(const scene_t *s, uint32_t q, vec_t *out, int64_t *count)
     if (c->hot_fraction > 0.0 && c->hot_rate_hz > 0.0) {
         uint64_t r = rng_key(c->seed, q, PURPOSE_HOT);
         if (rng_unif(&r) < c->hot_fraction) {
-            double rate = c->hot_rate_hz * 1e-6, t = 0.0;
+            double hz = c->hot_rate_hz;
+            if (c->hot_rate_hi_hz > hz)
+                hz *= exp(rng_unif(&r) * log(c->hot_rate_hi_hz / hz));
+            double rate = hz * 1e-6, t = 0.0;
             for (;;) {
                 t += -log(1.0 - rng_unif(&r)) / rate;
                 if (t >= (double)D)

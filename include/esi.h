@@ -121,9 +121,12 @@ typedef struct {
 typedef struct esi_state esi_state;
 
 /* Create a state for a W x H sensor: S = 0, T = t0_us, N = P = 0 (Alg. 1/2
- * initialisation).  1 <= W, H <= 65535 and W*H <= 4096000 (e.g. 2560 x 1600).
- * The state lives on the current HIP device.  On success *out receives the
- * state; the initialisation is enqueued on `stream`. */
+ * initialisation).  1 <= W, H <= 65536 (every 16-bit coordinate).  The state
+ * lives on the current HIP device (24 B per pixel: 103 GB for 65536 x 65536;
+ * ESI_ERR_OUT_OF_MEMORY if it does not fit).  A sensor of more than 4096000
+ * pixels is integrated in bands of rows of at most that many pixels, one pass
+ * over the events per band.  On success *out receives the state; the
+ * initialisation is enqueued on `stream`. */
 esi_status esi_create_state(int32_t width, int32_t height, const esi_params *params,
                             hipStream_t stream, esi_state **out);
 
@@ -139,7 +142,10 @@ esi_status esi_reset(esi_state *st, hipStream_t stream);
  *   ev        device SoA events; ev->n may be 0.  Expected time-sorted; if
  *             not, the state is still that of array order, the frames of
  *             this call are unspecified and ESI_DIAG_UNSORTED is set.
- *   t_frames  device, n_frames non-decreasing times (us); NULL iff n_frames 0.
+ *   t_frames  n_frames non-decreasing times (us), in device or host memory
+ *             (host memory is detected with hipPointerGetAttributes and
+ *             copied to the library's scratch on `stream`; keep it unchanged
+ *             until the stream has consumed it); NULL iff n_frames is 0.
  *             Frame j includes the events with t <= t_frames[j] and the
  *             events of earlier calls.
  *   frames    device f32 [n_frames][H][W], or NULL.
@@ -178,9 +184,9 @@ esi_status esi_import_state(esi_state *st, const void *host_buf, size_t bytes);
 esi_status esi_get_diagnostics(esi_state *st, esi_diag *out);
 
 /* Tile size of the integration kernels for later calls on this state: 256,
- * 512, 1024 or 2048 pixels (the smallest allowed: a sensor whose tiles would
- * be more than 2000 gets the next larger size), or 0 for the default (the
- * smallest size with at most 2000 tiles).  N, P and T do not depend on it, S
+ * 512, 1024 or 2048 pixels (the smallest allowed: a sensor (or band) whose
+ * tiles would be more than 2000 gets the next larger size), or 0 for the
+ * default (the smallest size with at most 2000 tiles).  N, P and T do not depend on it, S
  * and frames only to rounding (decay bases are taken per chunk of a tile's
  * events); for calls with few events per tile larger tiles shorten the
  * per-tile chains of dependent memory accesses, for event-dense calls
@@ -219,12 +225,15 @@ esi_status esi_batch_destroy(esi_batch *batch);
 
 /* Item i integrates events[i] into states[i] and writes n_frames[i] frames
  * at t_frames[i] into frames[i] / frames_u8[i], with the rules of
- * esi_integrate_window for each item (all in device memory, all on the
- * batch's device).  states: n_items distinct states (host array of
+ * esi_integrate_window for each item (buffers in device memory of the
+ * batch's device, frame times in device or host memory).  states: n_items distinct states (host array of
  * pointers); events: host array of n_items descriptors.  t_frames, n_frames,
  * frames, frames_u8: host arrays of n_items entries, or NULL for "no frames"
  * / "no such output" for every item.  1 <= n_items <= max_items.  Argument
- * errors return ESI_ERR_INVALID_ARG before anything is enqueued; a poisoned
+ * errors return ESI_ERR_INVALID_ARG before anything is enqueued (also for a
+ * state of more than 4096000 pixels, which only esi_integrate_window
+ * integrates, band by band); t_frames[i] may be host memory (packed into the
+ * batch's staging and copied with the descriptors); a poisoned
  * state returns ESI_ERR_POISONED; a HIP failure poisons every state of the
  * call.  The call may wait for the previous call's descriptor copy (host
  * side) and for the stream when a state's scratch must grow; its descriptor

@@ -61,6 +61,10 @@ def load(path: str = _LIB) -> ctypes.CDLL:
                                          P, P, P, P, i64, P, P, P, P, i32, P, P,
                                          P, P, P]
     lib.esi_oracle_integrate.restype = None
+    lib.esi_oracle_integrate_rows.argtypes = [i32, i32, i32, i32, f64, f64, f64, f64, f64,
+                                              u32, P, P, P, P, i64, P, P, P, P, i32, P, P,
+                                              P, P, P]
+    lib.esi_oracle_integrate_rows.restype = None
     if path == _LIB:
         _lib = lib
     return lib
@@ -160,6 +164,50 @@ class State:
             _ptr(sel), _ptr(frames), ctypes.byref(dropped), ctypes.byref(unsorted))
         self.dropped += dropped.value
         self.unsorted = self.unsorted or bool(unsorted.value)
+        return frames
+
+    def integrate_rows(self, x, y, t, p, t_frames=None, frame_sel=None,
+                       want_frames: bool = True, threads: int = 1):
+        """The same result as integrate(), computed by `threads` host threads,
+        each running the oracle's event loop over all events for its own band
+        of rows (pixels are independent, so the bands are too).  Used to time
+        the oracle on every host core; the serial loop stays the reference."""
+        from concurrent.futures import ThreadPoolExecutor
+        x = np.ascontiguousarray(x, dtype=np.uint16)
+        y = np.ascontiguousarray(y, dtype=np.uint16)
+        t = np.ascontiguousarray(t, dtype=np.int64)
+        p = np.ascontiguousarray(p, dtype=np.int8)
+        n = x.size
+        tf = (np.zeros(0, np.int64) if t_frames is None
+              else np.ascontiguousarray(t_frames, dtype=np.int64))
+        nf = tf.size
+        sel = None
+        nsel = nf
+        if frame_sel is not None:
+            sel = np.zeros(nf, np.uint8)
+            sel[np.asarray(frame_sel, dtype=np.int64)] = 1
+            nsel = int(sel.sum())
+        frames = None
+        if want_frames and nsel > 0:
+            frames = np.empty((nsel, self.H, self.W), np.float64)
+        nb = max(1, min(int(threads), self.H))
+        cuts = [self.H * i // nb for i in range(nb + 1)]
+        drops = [ctypes.c_uint64(0) for _ in range(nb)]
+        unsorted = [ctypes.c_int32(0) for _ in range(nb)]
+        pr = self.params
+
+        def band(i):
+            # ctypes releases the interpreter lock for the duration of the call
+            self.lib.esi_oracle_integrate_rows(
+                self.W, self.H, cuts[i], cuts[i + 1], pr.C, pr.k_per_us, pr.b, pr.s_min,
+                pr.s_max, pr.flags, _ptr(self.S), _ptr(self.T), _ptr(self.N), _ptr(self.P),
+                n, _ptr(x), _ptr(y), _ptr(t), _ptr(p), nf, _ptr(tf) if nf else None,
+                _ptr(sel), _ptr(frames), ctypes.byref(drops[i]), ctypes.byref(unsorted[i]))
+
+        with ThreadPoolExecutor(max_workers=nb) as ex:
+            list(ex.map(band, range(nb)))
+        self.dropped += sum(d.value for d in drops)
+        self.unsorted = self.unsorted or any(u.value for u in unsorted)
         return frames
 
     def snapshot(self, t_frame: int):

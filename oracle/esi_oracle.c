@@ -135,6 +135,83 @@ uint8_t esi_oracle_u8(double F)
     return (uint8_t)r;
 }
 
+/* A frame's rows [r0, r1) of the state at t_f (Eq. (14)); the part of
+ * esi_oracle_snapshot that one row band owns. */
+static void snapshot_rows(int32_t W, int32_t r0, int32_t r1, const double *S,
+                          const int64_t *T, int64_t t_f, double k, double b,
+                          double s_min, double s_max, uint32_t flags, double *frame)
+{
+    for (int64_t q = (int64_t)r0 * W; q < (int64_t)r1 * W; ++q)
+        frame[q] = frame_value(S[q], T[q], t_f, k, b, s_min, s_max, flags);
+}
+
+/*
+ * Alg. 2's event loop restricted to the pixels of rows [r0, r1): the events
+ * of other rows are passed over (each pixel's update reads and writes only
+ * that pixel, so the bands of a sensor are independent), and the frames are
+ * written for these rows only.  Out-of-range events are counted by the band
+ * that starts at row 0, decreasing times by every band.  The arguments are
+ * those of esi_oracle_integrate below, which is this loop over all rows.
+ */
+void esi_oracle_integrate_rows(int32_t W, int32_t H, int32_t r0, int32_t r1,
+                               double C, double k, double b, double s_min,
+                               double s_max, uint32_t flags, double *S,
+                               int64_t *T, uint32_t *N, int32_t *P, int64_t n,
+                               const uint16_t *x, const uint16_t *y,
+                               const int64_t *t, const int8_t *p, int32_t nf,
+                               const int64_t *t_frames, const uint8_t *frame_sel,
+                               double *frames, uint64_t *dropped, int32_t *unsorted)
+{
+    const int64_t npix = (int64_t)W * (int64_t)H;
+    int32_t j = 0;
+    int64_t nsel = 0;
+
+    for (int64_t i = 0; i < n; ++i) {
+        /* Frames strictly before this event's time see none of it. */
+        while (j < nf && t_frames[j] < t[i]) {
+            if (!frame_sel || frame_sel[j]) {
+                if (frames)
+                    snapshot_rows(W, r0, r1, S, T, t_frames[j], k, b, s_min,
+                                  s_max, flags, frames + nsel * npix);
+                ++nsel;
+            }
+            ++j;
+        }
+        if (i > 0 && t[i] < t[i - 1])
+            *unsorted = 1;
+        if (x[i] >= W || y[i] >= H) {
+            if (r0 == 0)
+                ++*dropped;
+            continue;
+        }
+        if (y[i] < r0 || y[i] >= r1)
+            continue;
+        const int64_t q = (int64_t)y[i] * W + x[i];
+        const int pol = (p[i] > 0) ? 1 : -1;
+        int64_t dt = t[i] - T[q];
+        if (dt < 0)
+            dt = 0;
+        const double d = decay_of((double)dt, k, b, flags);
+        if (flags & ORACLE_DECAY_THEN_ADD)
+            S[q] = S[q] * d + pol * C;
+        else
+            S[q] = (S[q] + pol * C) * d;
+        T[q] = t[i];
+        S[q] = clamp_s(S[q], s_min, s_max);
+        N[q] += 1;
+        P[q] += pol;
+    }
+    while (j < nf) {
+        if (!frame_sel || frame_sel[j]) {
+            if (frames)
+                snapshot_rows(W, r0, r1, S, T, t_frames[j], k, b, s_min, s_max,
+                              flags, frames + nsel * npix);
+            ++nsel;
+        }
+        ++j;
+    }
+}
+
 /*
  * Integrate n events into the state (Alg. 2's event loop) and emit frames.
  *
@@ -156,49 +233,7 @@ void esi_oracle_integrate(int32_t W, int32_t H, double C, double k, double b,
                           const int64_t *t_frames, const uint8_t *frame_sel,
                           double *frames, uint64_t *dropped, int32_t *unsorted)
 {
-    const int64_t npix = (int64_t)W * (int64_t)H;
-    int32_t j = 0;
-    int64_t nsel = 0;
-
-    for (int64_t i = 0; i < n; ++i) {
-        /* Frames strictly before this event's time see none of it. */
-        while (j < nf && t_frames[j] < t[i]) {
-            if (!frame_sel || frame_sel[j]) {
-                if (frames)
-                    esi_oracle_snapshot(npix, S, T, t_frames[j], k, b, s_min,
-                                        s_max, flags, frames + nsel * npix);
-                ++nsel;
-            }
-            ++j;
-        }
-        if (i > 0 && t[i] < t[i - 1])
-            *unsorted = 1;
-        if (x[i] >= W || y[i] >= H) {
-            ++*dropped;
-            continue;
-        }
-        const int64_t q = (int64_t)y[i] * W + x[i];
-        const int pol = (p[i] > 0) ? 1 : -1;
-        int64_t dt = t[i] - T[q];
-        if (dt < 0)
-            dt = 0;
-        const double d = decay_of((double)dt, k, b, flags);
-        if (flags & ORACLE_DECAY_THEN_ADD)
-            S[q] = S[q] * d + pol * C;
-        else
-            S[q] = (S[q] + pol * C) * d;
-        T[q] = t[i];
-        S[q] = clamp_s(S[q], s_min, s_max);
-        N[q] += 1;
-        P[q] += pol;
-    }
-    while (j < nf) {
-        if (!frame_sel || frame_sel[j]) {
-            if (frames)
-                esi_oracle_snapshot(npix, S, T, t_frames[j], k, b, s_min, s_max,
-                                    flags, frames + nsel * npix);
-            ++nsel;
-        }
-        ++j;
-    }
+    esi_oracle_integrate_rows(W, H, 0, H, C, k, b, s_min, s_max, flags, S, T, N,
+                              P, n, x, y, t, p, nf, t_frames, frame_sel, frames,
+                              dropped, unsorted);
 }

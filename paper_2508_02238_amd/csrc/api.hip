@@ -47,13 +47,20 @@ struct esi_batch {
     hipEvent_t copied = nullptr;  // recorded after the last staging copy
     hipEvent_t used = nullptr;    // recorded after the last call's kernels
     bool pending = false;
+    // frame times given in host memory, staged with the descriptors
+    void* tf_host = nullptr;
+    void* tf_dev = nullptr;
+    size_t tf_cap = 0;
 };
 
 namespace {
 
 constexpr uint64_t kMagic = 0x3130495345ull;  // "ESI01"
 constexpr uint32_t kProfMax = 1024;
+// pixels of one pass of the kernels (kMaxTiles tiles of 2048 pixels); larger
+// sensors are integrated in bands of rows, one pass each
 constexpr int64_t kMaxPixels = (int64_t)kMaxTiles * 256 * 8;  // 4096000
+constexpr int32_t kMaxSide = 65536;
 constexpr int32_t kMaxBatch = 4096;  // streams per batched call
 
 struct SerialHeader {
@@ -136,15 +143,35 @@ esi_status hip_fail(esi_state* st)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// The scratch of one call with n > 0 events under schedule sc: table |
-// segment sums | tile totals | total | records, grown on demand (after the
-// stream has finished with the old one).
-esi_status call_scratch(esi_state* st, const Schedule& sc, int64_t n, hipStream_t stream,
-                        CallScratch& cs)
+// Rows per pass of the kernels: the whole sensor when it fits one pass,
+// else the most rows whose pixels fit.
+int64_t band_rows(int32_t W, int32_t H)
 {
-    const int64_t M = (int64_t)sc.ntiles * sc.nunits;
-    const int64_t nseg = (int64_t)scan_segments(sc.nunits);
-    const size_t o_bs = align_up(4 * (size_t)M, 256);
+    return ((int64_t)W * H <= kMaxPixels) ? (int64_t)H : kMaxPixels / W;
+}
+
+// Frame times given in host memory are staged on the device.
+bool device_accessible(const void* p)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // plain pageable host memory
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.isManaged;
+}
+
+// The scratch of one call under schedule sc (n events; nf_stage frame times
+// staged from host memory): frame times | table | segment sums | tile totals
+// | total | records, grown on demand (after the stream has finished with the
+// old one).
+esi_status call_scratch(esi_state* st, const Schedule& sc, int64_t n, int32_t nf_stage,
+                        hipStream_t stream, CallScratch& cs, int64_t** tf_stage)
+{
+    const int64_t M = n > 0 ? (int64_t)sc.ntiles * sc.nunits : 0;
+    const int64_t nseg = n > 0 ? (int64_t)scan_segments(sc.nunits) : 0;
+    const size_t o_tab = align_up(8 * (size_t)nf_stage, 256);
+    const size_t o_bs = o_tab + align_up(4 * (size_t)M, 256);
     const size_t o_tt = o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
     const size_t o_tot = o_tt + align_up(4 * (size_t)sc.ntiles, 256);
     const size_t o_rec = o_tot + 256;
@@ -165,12 +192,29 @@ esi_status call_scratch(esi_state* st, const Schedule& sc, int64_t n, hipStream_
         st->scratch_bytes = bytes;
     }
     char* base = (char*)st->scratch;
-    cs.table = (uint32_t*)base;
+    if (tf_stage)
+        *tf_stage = (int64_t*)base;
+    cs.table = (uint32_t*)(base + o_tab);
     cs.blocksum = (uint32_t*)(base + o_bs);
     cs.tile_tot = (uint32_t*)(base + o_tt);
     cs.total = (uint32_t*)(base + o_tot);
     cs.records = (uint64_t*)(base + o_rec);
     return ESI_OK;
+}
+
+// The state of rows [y0, y0 + rows) as a state of its own (one pass).
+StateDev band_state(const StateDev& d, int64_t y0, int64_t rows)
+{
+    const int64_t off = y0 * d.W;
+    StateDev b = d;
+    b.S_hi += off;
+    b.S_lo += off;
+    b.T += off;
+    b.N += off;
+    b.P += off;
+    b.H = (int)rows;
+    b.npix = rows * d.W;
+    return b;
 }
 
 }  // namespace
@@ -200,11 +244,9 @@ esi_status esi_create_state(int32_t width, int32_t height, const esi_params* par
     if (!out)
         return ESI_ERR_INVALID_ARG;
     *out = nullptr;
-    if (width < 1 || height < 1 || width > 65535 || height > 65535 || !params_ok(params))
+    if (width < 1 || height < 1 || width > kMaxSide || height > kMaxSide || !params_ok(params))
         return ESI_ERR_INVALID_ARG;
     const int64_t npix = (int64_t)width * height;
-    if (npix > kMaxPixels)
-        return ESI_ERR_INVALID_ARG;
     esi_state* st = new (std::nothrow) esi_state();
     if (!st)
         return ESI_ERR_OUT_OF_MEMORY;
@@ -236,7 +278,8 @@ esi_status esi_create_state(int32_t width, int32_t height, const esi_params* par
     st->dev.H = height;
     st->dev.npix = npix;
     st->diag = (DiagDev*)(base + o_diag);
-    st->bucket_slots = bucket_slots(make_schedule(npix, 0, 1).ntiles);
+    st->bucket_slots =
+        bucket_slots(make_schedule(band_rows(width, height) * width, 0, 1).ntiles);
     if (launch_reset(st->dev, params->t0_us, st->diag, stream) != hipSuccess) {
         (void)hipFree(st->state_mem);
         delete st;
@@ -345,13 +388,26 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
     MethodParams mp = method_params(st->params);
     if (!st->state_in_range)
         mp.need_clamp = 1;
-    const Schedule sc = make_schedule(st->npix, n, st->bucket_slots, st->min_ppt);
-    EventsDev evd{ev->x, ev->y, ev->t, ev->p, n};
+    // the sensor in bands of rows, one pass of the kernels each (one band
+    // unless the sensor is larger than a pass holds); the first band is the
+    // largest, so its scratch serves every band
+    const int64_t rows = band_rows(st->W, st->H);
+    const bool stage_tf = n_frames > 0 && !device_accessible(t_frames);
+    const Schedule sc0 = make_schedule(rows * st->W, n, st->bucket_slots, st->min_ppt);
     CallScratch cs{};
-    if (n > 0) {
-        const esi_status rc = call_scratch(st, sc, n, stream, cs);
+    int64_t* tf_dev = nullptr;
+    if (n > 0 || stage_tf) {
+        const esi_status rc =
+            call_scratch(st, sc0, n, stage_tf ? n_frames : 0, stream, cs, &tf_dev);
         if (rc != ESI_OK)
             return rc;
+    }
+    const int64_t* tf = t_frames;
+    if (stage_tf) {
+        if (hipMemcpyAsync(tf_dev, t_frames, 8 * (size_t)n_frames, hipMemcpyHostToDevice,
+                           stream) != hipSuccess)
+            return hip_fail(st);
+        tf = tf_dev;
     }
     hipEvent_t* pe = nullptr;
     if (st->profiling && st->prof_calls < kProfMax) {
@@ -359,14 +415,23 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
         if (hipEventRecord(pe[0], stream) != hipSuccess)
             return hip_fail(st);
     }
-    if (n > 0 && launch_bucket(evd, st->dev, sc, cs, st->diag, stream) != hipSuccess)
-        return hip_fail(st);
-    if (pe && hipEventRecord(pe[1], stream) != hipSuccess)
-        return hip_fail(st);
-    if (n > 0 || n_frames > 0) {
-        if (launch_integrate(evd, st->dev, sc, cs, mp, t_frames, n_frames, frames, frames_u8,
-                             st->diag, stream) != hipSuccess)
+    for (int64_t y0 = 0; y0 < st->H; y0 += rows) {
+        const int64_t hb = std::min<int64_t>(rows, st->H - y0);
+        const StateDev sd = band_state(st->dev, y0, hb);
+        const Schedule sc = make_schedule(sd.npix, n, st->bucket_slots, st->min_ppt);
+        const EventsDev evd{ev->x, ev->y, ev->t, ev->p, n, (int)y0, st->H};
+        const int64_t off = y0 * st->W;
+        const FrameOut fo{tf, n_frames, frames ? frames + off : nullptr,
+                          frames_u8 ? frames_u8 + off : nullptr, st->npix};
+        if (n > 0 && launch_bucket(evd, sd, sc, cs, st->diag, stream) != hipSuccess)
             return hip_fail(st);
+        // the bucketing time of a banded call is its first band's
+        if (pe && y0 == 0 && hipEventRecord(pe[1], stream) != hipSuccess)
+            return hip_fail(st);
+        if (n > 0 || n_frames > 0) {
+            if (launch_integrate(evd, sd, sc, cs, mp, fo, st->diag, stream) != hipSuccess)
+                return hip_fail(st);
+        }
     }
     if (pe && hipEventRecord(pe[2], stream) != hipSuccess)
         return hip_fail(st);
@@ -534,6 +599,10 @@ size_t batch_bytes(int32_t m) { return batch_items_bytes(m) + 3 * batch_base_byt
 
 void batch_free(esi_batch* b)
 {
+    if (b->tf_dev)
+        (void)hipFree(b->tf_dev);
+    if (b->tf_host)
+        (void)hipHostFree(b->tf_host);
     if (b->copied)
         (void)hipEventDestroy(b->copied);
     if (b->used)
@@ -622,6 +691,10 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
             return ESI_ERR_INVALID_ARG;
         if ((nf > 0) != (tf != nullptr) || (nf > 0 && !fr && !u8))
             return ESI_ERR_INVALID_ARG;
+        // a sensor larger than one pass of the kernels is integrated in bands
+        // by esi_integrate_window only
+        if (st->npix > kMaxPixels)
+            return ESI_ERR_INVALID_ARG;
         n_all += (int64_t)ev.n;
     }
     {
@@ -655,7 +728,7 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         sc[i] = make_schedule(st->npix, n, share, st->min_ppt);
         BatchItem& x = it[i];
         x = BatchItem{};
-        x.ev = EventsDev{events[i].x, events[i].y, events[i].t, events[i].p, n};
+        x.ev = EventsDev{events[i].x, events[i].y, events[i].t, events[i].p, n, 0, st->H};
         x.st = st->dev;
         x.mp = method_params(st->params);
         if (!st->state_in_range)
@@ -663,12 +736,12 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         const int32_t nf = n_frames ? n_frames[i] : 0;
         x.fo = FrameOut{nf > 0 ? t_frames[i] : nullptr, nf,
                         (nf > 0 && frames) ? frames[i] : nullptr,
-                        (nf > 0 && frames_u8) ? frames_u8[i] : nullptr};
+                        (nf > 0 && frames_u8) ? frames_u8[i] : nullptr, st->npix};
         x.diag = st->diag;
         x.tile_log = sc[i].tile_log;
         x.K = sc[i].ntiles;
         if (n > 0) {
-            const esi_status rc = call_scratch(st, sc[i], n, stream, x.cs);
+            const esi_status rc = call_scratch(st, sc[i], n, 0, stream, x.cs, nullptr);
             if (rc != ESI_OK)
                 return rc;
             x.E = sc[i].unit_events;
@@ -689,6 +762,38 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
     const bool earlier = b->pending;
     if (earlier && hipEventSynchronize(b->copied) != hipSuccess)
         return ESI_ERR_HIP;
+    // frame times in host memory: packed into the batch's own staging and
+    // copied with the descriptors
+    size_t tf_bytes = 0;
+    std::vector<size_t> tf_off(n_items, SIZE_MAX);
+    for (int32_t i = 0; i < n_items; ++i)
+        if (it[i].fo.nf > 0 && !device_accessible(it[i].fo.t_frames)) {
+            tf_off[i] = tf_bytes;
+            tf_bytes += align_up(8 * (size_t)it[i].fo.nf, 64);
+        }
+    if (tf_bytes > b->tf_cap) {
+        // earlier calls' kernels may still read the device copy
+        if (earlier && hipEventSynchronize(b->used) != hipSuccess)
+            return ESI_ERR_HIP;
+        if (b->tf_dev)
+            (void)hipFree(b->tf_dev);
+        if (b->tf_host)
+            (void)hipHostFree(b->tf_host);
+        b->tf_dev = b->tf_host = nullptr;
+        b->tf_cap = 0;
+        const size_t cap = tf_bytes + tf_bytes / 4;
+        if (hipHostMalloc(&b->tf_host, cap, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&b->tf_dev, cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return ESI_ERR_OUT_OF_MEMORY;
+        }
+        b->tf_cap = cap;
+    }
+    for (int32_t i = 0; i < n_items; ++i)
+        if (tf_off[i] != SIZE_MAX) {
+            std::memcpy((char*)b->tf_host + tf_off[i], it[i].fo.t_frames, 8 * (size_t)it[i].fo.nf);
+            it[i].fo.t_frames = (const int64_t*)((char*)b->tf_dev + tf_off[i]);
+        }
     char* h = (char*)b->host;
     BatchItem* hi = (BatchItem*)h;
     uint32_t* ub = (uint32_t*)(h + batch_items_bytes(b->max_items));
@@ -718,6 +823,8 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
     // device descriptors until they finish
     if ((earlier && hipStreamWaitEvent(stream, b->used, 0) != hipSuccess) ||
         hipMemcpyAsync(b->dev, b->host, b->bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        (tf_bytes > 0 && hipMemcpyAsync(b->tf_dev, b->tf_host, tf_bytes, hipMemcpyHostToDevice,
+                                        stream) != hipSuccess) ||
         hipEventRecord(b->copied, stream) != hipSuccess)
         return fail();
     b->pending = true;

@@ -52,10 +52,15 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
     return x * q + (x < r ? x : r) + i;
 }
 
-__device__ __forceinline__ bool valid_q(uint32_t x, uint32_t y, int W, int H, uint32_t& q)
+// An event of this pass: x < W and y in the pass's rows [y0, y0 + H); q is
+// its pixel inside the pass.  `drop`: the event is off the sensor.
+__device__ __forceinline__ bool valid_q(uint32_t x, uint32_t y, int W, int H, const EventsDev& ev,
+                                        uint32_t& q, bool& drop)
 {
-    q = y * (uint32_t)W + x;
-    return x < (uint32_t)W && y < (uint32_t)H;
+    const uint32_t yl = y - (uint32_t)ev.y0;
+    q = yl * (uint32_t)W + x;
+    drop = x >= (uint32_t)W || y >= (uint32_t)ev.H_all;
+    return x < (uint32_t)W && yl < (uint32_t)H;
 }
 
 // Range `unit` holds events [unit E, min((unit + 1) E, n)); E is a multiple
@@ -89,29 +94,28 @@ __device__ __forceinline__ void hist_body(const EventsDev& ev, int W, int H, int
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 uint32_t q;
-                if (valid_q(xs[m] & 0xFFFFu, ys[m] & 0xFFFFu, W, H, q))
+                bool off;
+                if (valid_q(xs[m] & 0xFFFFu, ys[m] & 0xFFFFu, W, H, ev, q, off))
                     atomicAdd(&h[q >> tile_log], 1u);
-                else
-                    ++drop;
-                if (valid_q(xs[m] >> 16, ys[m] >> 16, W, H, q))
+                drop += off;
+                if (valid_q(xs[m] >> 16, ys[m] >> 16, W, H, ev, q, off))
                     atomicAdd(&h[q >> tile_log], 1u);
-                else
-                    ++drop;
+                drop += off;
             }
         }
     }
     for (int64_t e = i + threadIdx.x; e < hi; e += NT) {
         uint32_t q;
-        if (valid_q(ev.x[e], ev.y[e], W, H, q))
+        bool off;
+        if (valid_q(ev.x[e], ev.y[e], W, H, ev, q, off))
             atomicAdd(&h[q >> tile_log], 1u);
-        else
-            ++drop;
+        drop += off;
     }
     __syncthreads();
     uint32_t* row = table + unit * K;
     for (int k = threadIdx.x; k < K; k += NT)
         row[k] = h[k];
-    if (drop)
+    if (drop && ev.y0 == 0)
         atomicAdd(&diag->dropped, (unsigned long long)drop);
 }
 
@@ -289,8 +293,9 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
 #pragma unroll
             for (int s = 0; s < BATCH; ++s) {
                 const bool in = w0 + (b0 + s) * kWave + lane < nsb;
-                const uint32_t q = __umul24(ys[s], (uint32_t)W) + xs[s];
-                const bool ok = in && xs[s] < (uint32_t)W && ys[s] < (uint32_t)H;
+                const uint32_t yl = ys[s] - (uint32_t)ev.y0;
+                const uint32_t q = yl * (uint32_t)W + xs[s];
+                const bool ok = in && xs[s] < (uint32_t)W && yl < (uint32_t)H;
                 const int64_t t = ts[s];
                 // decreasing time versus the previous event in array order:
                 // the previous lane's time (lane 0: the previous step's last)

@@ -39,12 +39,19 @@ struct CallScratch {
     uint64_t* records;    // [n]
 };
 
+// Events of one call.  A sensor larger than one pass of the kernels holds is
+// integrated in bands of rows: a pass takes the events with y in
+// [y0, y0 + H) of the band's state (H = StateDev::H), passes over the other
+// rows' events, and counts an event as dropped (x >= W or y >= H_all) only in
+// the pass with y0 = 0.
 struct EventsDev {
     const uint16_t* x;
     const uint16_t* y;
     const int64_t* t;
     const int8_t* p;
     int64_t n;
+    int y0;     // first row of the pass
+    int H_all;  // rows of the sensor
 };
 
 struct StateDev {
@@ -58,12 +65,14 @@ struct StateDev {
 };
 
 // Frames of one call: times (device), count, FP32 and 8-bit outputs (either
-// may be null).
+// may be null; they point at the pass's first pixel), and the pixels from
+// one frame to the next (the whole sensor's W * H).
 struct FrameOut {
     const int64_t* t_frames;
     int nf;
     float* frames;
     uint8_t* frames_u8;
+    int64_t stride;
 };
 
 // One stream of a batched call: everything its kernels read, in device
@@ -99,8 +108,7 @@ size_t scan_segments(int64_t B);
 hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule& sc,
                          const CallScratch& cs, DiagDev* diag, hipStream_t stream);
 hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Schedule& sc,
-                            const CallScratch& cs, const MethodParams& mp,
-                            const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
+                            const CallScratch& cs, const MethodParams& mp, const FrameOut& fo,
                             DiagDev* diag, hipStream_t stream);
 hipError_t launch_snapshot(const StateDev& st, const MethodParams& mp, int64_t t_f, float* frame,
                            uint8_t* u8, hipStream_t stream);

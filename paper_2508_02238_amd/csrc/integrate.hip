@@ -658,10 +658,10 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         // 4. phase B: the frames this chunk completes
         if (nfw > 0) {
-            const size_t base = (size_t)j * (size_t)npix + (size_t)tile * TILE;
+            const size_t base = (size_t)j * (size_t)fo.stride + (size_t)tile * TILE;
             walk_dispatch<PPT, NB, BK>(mode, mp, px, nfw, ktv0, ktv1, chg_S, chg_A, chg_j,
                                    fo.frames ? fo.frames + base : nullptr,
-                                   fo.frames_u8 ? fo.frames_u8 + base : nullptr, npix,
+                                   fo.frames_u8 ? fo.frames_u8 + base : nullptr, fo.stride,
                                    4u * tile_px, tile_px);
         }
         j = j_end;
@@ -782,11 +782,9 @@ __global__ __launch_bounds__(kBlock) void k_reset(StateDev st, int64_t t0, DiagD
 
 template <int PPT, int NB, int BK>
 hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Schedule& sc,
-                              const CallScratch& cs, const MethodParams& mp,
-                              const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
+                              const CallScratch& cs, const MethodParams& mp, const FrameOut& fo,
                               DiagDev* diag, hipStream_t stream)
 {
-    FrameOut fo{t_frames, nf, frames, frames_u8};
     const bool has = ev.n > 0;
     hipLaunchKernelGGL((k_integrate<PPT, NB, BK>), dim3(sc.ntiles), dim3(NB), 0, stream,
                        has ? cs.records : nullptr, has ? cs.table : nullptr,
@@ -796,23 +794,18 @@ hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Sch
 
 template <int PPT, int NB>
 hipError_t launch_integrate_p(const EventsDev& ev, const StateDev& st, const Schedule& sc,
-                              const CallScratch& cs, const MethodParams& mp,
-                              const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
+                              const CallScratch& cs, const MethodParams& mp, const FrameOut& fo,
                               DiagDev* diag, hipStream_t stream)
 {
     switch (decay_kind(mp)) {
     case kDecayB1:
-        return launch_integrate_t<PPT, NB, kDecayB1>(ev, st, sc, cs, mp, t_frames, nf, frames,
-                                                 frames_u8, diag, stream);
+        return launch_integrate_t<PPT, NB, kDecayB1>(ev, st, sc, cs, mp, fo, diag, stream);
     case kDecayB2:
-        return launch_integrate_t<PPT, NB, kDecayB2>(ev, st, sc, cs, mp, t_frames, nf, frames,
-                                                 frames_u8, diag, stream);
+        return launch_integrate_t<PPT, NB, kDecayB2>(ev, st, sc, cs, mp, fo, diag, stream);
     case kDecayExp:
-        return launch_integrate_t<PPT, NB, kDecayExp>(ev, st, sc, cs, mp, t_frames, nf, frames,
-                                                  frames_u8, diag, stream);
+        return launch_integrate_t<PPT, NB, kDecayExp>(ev, st, sc, cs, mp, fo, diag, stream);
     default:
-        return launch_integrate_t<PPT, NB, kDecayPow>(ev, st, sc, cs, mp, t_frames, nf, frames,
-                                                  frames_u8, diag, stream);
+        return launch_integrate_t<PPT, NB, kDecayPow>(ev, st, sc, cs, mp, fo, diag, stream);
     }
 }
 
@@ -826,24 +819,19 @@ int decay_kind(const MethodParams& mp)
 }
 
 hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Schedule& sc,
-                            const CallScratch& cs, const MethodParams& mp,
-                            const int64_t* t_frames, int nf, float* frames, uint8_t* frames_u8,
+                            const CallScratch& cs, const MethodParams& mp, const FrameOut& fo,
                             DiagDev* diag, hipStream_t stream)
 {
     switch (sc.ppt) {
     // 256 threads per tile, 1, 2, 4 or 8 pixels each
     case 1:
-        return launch_integrate_p<1, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
-                                          stream);
+        return launch_integrate_p<1, 256>(ev, st, sc, cs, mp, fo, diag, stream);
     case 2:
-        return launch_integrate_p<2, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
-                                          stream);
+        return launch_integrate_p<2, 256>(ev, st, sc, cs, mp, fo, diag, stream);
     case 4:
-        return launch_integrate_p<4, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
-                                          stream);
+        return launch_integrate_p<4, 256>(ev, st, sc, cs, mp, fo, diag, stream);
     case 8:
-        return launch_integrate_p<8, 256>(ev, st, sc, cs, mp, t_frames, nf, frames, frames_u8, diag,
-                                          stream);
+        return launch_integrate_p<8, 256>(ev, st, sc, cs, mp, fo, diag, stream);
     default:
         return hipErrorInvalidValue;
     }

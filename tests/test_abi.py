@@ -40,7 +40,8 @@ def test_status_strings():
     assert "UNKNOWN" in esi.esi_status_string(99)
 
 
-@pytest.mark.parametrize("w,h,kw", [(0, 4, {}), (4, 0, {}), (70000, 4, {}), (4000, 4000, {}),
+@pytest.mark.parametrize("w,h,kw", [(0, 4, {}), (4, 0, {}), (70000, 4, {}), (65537, 4, {}),
+                                    (4, 65537, {}),
                                     (4, 4, dict(C=0.0)), (4, 4, dict(b=0.0)),
                                     (4, 4, dict(k_per_us=-1e-6)),
                                     (4, 4, dict(s_min=1.0, s_max=1.0)),

@@ -149,3 +149,43 @@ def test_tile_size_keeps_results(esi, W, H):
         st.close()
     assert esi.esi_set_tile_pixels(None, 256) == esi.ESI_ERR_INVALID_ARG
     assert esi.esi_set_tile_pixels(None, 300) == esi.ESI_ERR_INVALID_ARG
+
+
+def test_c4_preset_matches_oracle(esi):
+    """The batched workload (64 streams of mixed size and rate, one batched
+    call per 10 ms window with one frame per stream) over four windows:
+    every stream's frames and final state against the oracle."""
+    import torch
+    win, nwin = 10_000, 4
+    streams = evgen.preset_batch("c4", duration_us=nwin * win)
+    prm = dict(C=0.2, k_per_us=2e-6, b=2.0, s_min=-1.0, s_max=1.0)
+    states = [esi.State(s.width, s.height, **prm) for s in streams]
+    batch = esi.Batch(len(streams))
+    frames = [[] for _ in streams]
+    for w in range(nwin):
+        evs, tfs = [], []
+        for s in streams:
+            ws = _window_of(s, w, win)
+            evs.append((ws.x, ws.y, ws.t, ws.p))
+            tfs.append(np.array([(w + 1) * win - 1], np.int64))
+        outs = batch.integrate(states, evs, tfs)
+        for i, (fr, _) in enumerate(outs):
+            frames[i].append(fr)
+    torch.cuda.synchronize()
+    tf = np.arange(1, nwin + 1, dtype=np.int64) * win - 1
+    for i, s in enumerate(streams):
+        full = s.slice(0, int(np.searchsorted(s.t, nwin * win, side="left")))
+        fo, o = oracle_run(full, prm, t_frames=tf)
+        S, T, N, P = (a.cpu().numpy() for a in states[i].read_state())
+        assert_state((S, T, N.view(np.uint32), P), o, prm["C"], f"stream {i}")
+        fg = torch.cat(frames[i]).cpu().numpy()
+        assert_frames(fg, fo, prm, f"stream {i}")
+    batch.close()
+    for st in states:
+        st.close()
+
+
+def _window_of(s, w, win):
+    lo = np.searchsorted(s.t, w * win, side="left")
+    hi = np.searchsorted(s.t, (w + 1) * win, side="left")
+    return s.slice(int(lo), int(hi))

@@ -382,3 +382,91 @@ def test_paper_scenes(esi, scene, k):
         prm = dict(C=0.2, k_per_us=k, b=2.0, s_min=-1e6, s_max=1e6)
         tf = np.array([1_000_000, 1_999_999], np.int64)
     _check(esi, s, prm, tf, where=f"{scene} k={k}")
+
+
+@pytest.mark.parametrize("flags,k,tf_us", [
+    # exponential decay: frames 0.1, 0.5, 2 and 10 s apart span more than 600
+    # decay lengths at k = 1e-3 /us, so every frame is a segment of its own
+    (4, 1e-3, [100_000, 500_000, 2_000_000, 10_000_000]),
+    (5, 1e-3, [100_000, 100_400, 500_000, 2_000_000, 2_000_700, 10_000_000]),
+    # Eq. (4): frames more than 2^30 / k apart (inside the 2^47 us a call's
+    # events may span), near frames between them
+    (0, 1e-3, [300_000, 300_500, 600_000, 2_000_000_000_000, 2_000_000_000_600,
+               100_000_000_000_000]),
+    (1, 2e-6, [400_000, 900_000, 700_000_000_000_000, 700_000_000_400_000]),
+])
+def test_long_gap_segments(esi, flags, k, tf_us):
+    """Frames far apart in decay lengths take the kernel's one-frame
+    segments: state and every frame against the oracle, in one call and in
+    calls whose events follow the far frames."""
+    prm = dict(C=0.2, k_per_us=k, b=2.0, s_min=-1.0, s_max=1.0, flags=flags)
+    tf = np.array(tf_us, np.int64)
+    # events up to just past the first frames, with same-time bursts
+    s = evgen.random_stream(seed=31 + flags, width=70, height=30, n=60_000,
+                            t_max=int(tf[1]) + 1, burst_frac=0.2)
+    _check(esi, s, prm, tf, u8=True, where=f"long gaps flags {flags}")
+    # a second call whose events come after the far frames: T jumps by more
+    # than 2^30 decay lengths, frames of both calls
+    late = evgen.random_stream(seed=41 + flags, width=70, height=30, n=20_000,
+                               t_min=int(tf[-1]) - 2_000, t_max=int(tf[-1]) + 3_000)
+    both = evgen.Stream(np.concatenate([s.x, late.x]), np.concatenate([s.y, late.y]),
+                        np.concatenate([s.t, late.t]), np.concatenate([s.p, late.p]),
+                        70, 30, int(tf[-1]) + 3_000)
+    tf2 = np.concatenate([tf[:-1], [int(tf[-1]) + 1_000, int(tf[-1]) + 3_000]]).astype(np.int64)
+    _check(esi, both, prm, tf2, calls=[(0, s.n), (s.n, both.n)], where=f"late flags {flags}")
+
+
+def test_host_frame_times(esi):
+    """Frame times in host memory (numpy, pageable; and pinned) give the
+    frames of the same times in device memory."""
+    import torch
+    s = evgen.random_stream(seed=51, width=90, height=40, n=80_000, t_max=500_000,
+                            burst_frac=0.1)
+    tf = np.arange(1, 51, dtype=np.int64) * 10_000
+    fo, o = oracle_run(s, DEFAULT, t_frames=tf)
+    dev = torch.device("cuda", 0)
+    args = [torch.from_numpy(a).to(dev) for a in (s.x.view(np.int16), s.y.view(np.int16), s.t,
+                                                    s.p)]
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    pinned = torch.from_numpy(tf).pin_memory()
+    for where, tf_ptr in (("pageable", tf.ctypes.data), ("pinned", pinned.data_ptr())):
+        st = esi.State(s.width, s.height, **DEFAULT)
+        fr = torch.empty((tf.size, s.height, s.width), dtype=torch.float32, device=dev)
+        rc = esi.esi_integrate_window(st.handle, *(a.data_ptr() for a in args), s.n, tf_ptr,
+                                      tf.size, fr.data_ptr(), None, stream)
+        assert rc == esi.ESI_OK, esi.esi_status_string(rc)
+        torch.cuda.synchronize()
+        assert_frames(fr.cpu().numpy(), fo, DEFAULT, where)
+        S, T, N, P = (a.cpu().numpy() for a in st.read_state())
+        assert_state((S, T, N.view(np.uint32), P), o, DEFAULT["C"], where)
+        st.close()
+
+
+@pytest.mark.parametrize("W,H", [(4000, 1100), (65536, 70)])
+def test_banded_sensor(esi, W, H):
+    """A sensor of more than 4096000 pixels is integrated in bands of rows
+    (one pass over the events each): state, dropped count and frames against
+    the oracle, with events on every band, off the sensor and in bursts."""
+    s = evgen.random_stream(seed=W + H, width=W, height=H, n=400_000, t_max=400_000,
+                            burst_frac=0.2, oob_frac=0.02 if W < 65536 else 0.0)
+    tf = np.array([100_000, 250_000, 400_000], np.int64)
+    fg, _, stg, diag = gpu_run(esi, s, DEFAULT, t_frames=tf)
+    fo, o = oracle_run(s, DEFAULT, t_frames=tf)
+    assert_state(stg, o, DEFAULT["C"], f"{W}x{H}")
+    assert_frames(fg, fo, DEFAULT, f"{W}x{H}")
+    assert diag["dropped"] == o.dropped
+    assert diag["accepted"] == s.n - o.dropped
+
+
+def test_hot_pixel_stress_workload(esi):
+    """The 1280x720 spoke workload plus hot pixels (0.01% of the sensor at
+    10-100 kHz: runs of 10^4 and more events per pixel) in the benchmark's
+    launch configuration: state and sampled frames."""
+    s = evgen.preset("c3hot")
+    tf = s.frame_times(100)
+    sel = [0, 250, 499]
+    fg, _, stg, diag = gpu_run(esi, s, DEFAULT, t_frames=tf, frame_sel=sel)
+    fo, o = oracle_run(s, DEFAULT, t_frames=tf, frame_sel=sel)
+    assert_state(stg, o, DEFAULT["C"], "c3hot")
+    assert_frames(fg, fo, DEFAULT, "c3hot")
+    assert diag["accepted"] == s.n - o.dropped

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import evgen
+from esi_parity import assert_frames, assert_state, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -89,6 +90,11 @@ def test_served_equals_alone(esi):
             assert torch.equal(a, b), i
         assert torch.equal(got_frame, fr), i
         alone.close()
+        # and the served session against the FP64 oracle over its packets
+        fo, o = oracle_run(streams[i], prm, t_frames=np.array([PACKETS * PACKET_US - 1], np.int64))
+        S, T, N, P = (a.cpu().numpy() for a in got_state)
+        assert_state((S, T, N.view(np.uint32), P), o, prm["C"], f"served {i}")
+        assert_frames(got_frame.cpu().numpy(), fo, prm, f"served {i}")
 
 
 def test_served_reuses_pooled_states(esi):

@@ -67,6 +67,7 @@ typedef enum {
     ESI_ERR_OUT_OF_MEMORY = 2,
     ESI_ERR_HIP = 3,
     ESI_ERR_POISONED = 4,
+    ESI_ERR_SCRATCH_LIMIT = 5, /* esi_integrate_window_noalloc: call too large */
 } esi_status;
 
 /* params.flags */
@@ -156,6 +157,27 @@ esi_status esi_reset(esi_state *st, hipStream_t stream);
 esi_status esi_integrate_window(esi_state *st, const esi_events *ev, const int64_t *t_frames,
                                 int32_t n_frames, float *frames, uint8_t *frames_u8,
                                 hipStream_t stream);
+
+/* esi_integrate_window for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the call's scratch (tile
+ * histogram, its scan and the 8-byte tile-bucketed event records) in a fixed
+ * 64 MiB array that the library holds in each GPU's memory until the process
+ * ends, so the call allocates and frees nothing.  The state must exist
+ * already (esi_create_state allocates it and looks the array up on its
+ * device); inputs and outputs are the caller's, as for esi_integrate_window,
+ * except that t_frames must be device memory (ESI_ERR_INVALID_ARG
+ * otherwise: nothing is staged).  A call whose scratch exceeds the array
+ * (about 8 bytes per event plus 4 bytes per (tile, bucketing range): some
+ * 7.9M events on a 1280 x 720 sensor, more on smaller ones) returns
+ * ESI_ERR_SCRATCH_LIMIT before anything is enqueued; split it into several
+ * calls.  Every call on one GPU uses that GPU's one array: calls that overlap
+ * on one GPU (different streams, different threads) race and must be
+ * serialised by the caller; each call initialises all of the scratch it
+ * reads, so nothing carries over from the previous call. */
+esi_status esi_integrate_window_noalloc(esi_state *st, const esi_events *ev,
+                                        const int64_t *t_frames, int32_t n_frames,
+                                        float *frames, uint8_t *frames_u8, hipStream_t stream);
 
 /* One frame of the current state at t_frame_us (Alg. 2's final loop with
  * Eq. (14); decayed to t_frame_us unless ESI_SNAPSHOT_LAZY).  frame: device

@@ -25,6 +25,7 @@ ESI_ERR_INVALID_ARG = 1
 ESI_ERR_OUT_OF_MEMORY = 2
 ESI_ERR_HIP = 3
 ESI_ERR_POISONED = 4
+ESI_ERR_SCRATCH_LIMIT = 5
 
 ESI_ADD_THEN_DECAY = 0
 ESI_DECAY_THEN_ADD = 1
@@ -65,6 +66,8 @@ _SIGNATURES = [
     ("esi_reset", ctypes.c_int, [_VP, _VP]),
     ("esi_integrate_window", ctypes.c_int, [_VP, ctypes.POINTER(esi_events), _VP,
                                             ctypes.c_int32, _VP, _VP, _VP]),
+    ("esi_integrate_window_noalloc", ctypes.c_int, [_VP, ctypes.POINTER(esi_events), _VP,
+                                                    ctypes.c_int32, _VP, _VP, _VP]),
     ("esi_snapshot_frame", ctypes.c_int, [_VP, ctypes.c_int64, _VP, _VP, _VP]),
     ("esi_read_state", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     ("esi_state_bytes", ctypes.c_size_t, [_VP]),
@@ -144,6 +147,14 @@ def esi_integrate_window(st, x_ptr, y_ptr, t_ptr, p_ptr, n, t_frames_ptr, n_fram
     return lib.esi_integrate_window(_VP(st), ctypes.byref(ev), _VP(t_frames_ptr),
                                     int(n_frames), _VP(frames_ptr), _VP(frames_u8_ptr),
                                     _VP(stream))
+
+
+def esi_integrate_window_noalloc(st, x_ptr, y_ptr, t_ptr, p_ptr, n, t_frames_ptr, n_frames,
+                                 frames_ptr, frames_u8_ptr, stream: int = 0) -> int:
+    ev = esi_events(x_ptr, y_ptr, t_ptr, p_ptr, int(n))
+    return lib.esi_integrate_window_noalloc(_VP(st), ctypes.byref(ev), _VP(t_frames_ptr),
+                                            int(n_frames), _VP(frames_ptr), _VP(frames_u8_ptr),
+                                            _VP(stream))
 
 
 def esi_set_tile_pixels(st, tile_pixels: int) -> int:

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -26,6 +27,9 @@ struct esi_state {
     // scratch of integrate calls, grown on demand
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // device address of the static scratch on this state's device (null if
+    // the lookup failed: esi_integrate_window_noalloc then returns ESI_ERR_HIP)
+    void* static_scratch = nullptr;
     int bucket_slots = 1024;  // bucketing workgroups resident at once
     int min_ppt = 1;          // smallest pixels per thread of the integration tiles
     bool state_in_range = true;  // every S in [s_min, s_max] (false after importing one outside)
@@ -52,6 +56,41 @@ struct esi_batch {
     void* tf_dev = nullptr;
     size_t tf_cap = 0;
 };
+
+// Scratch of esi_integrate_window_noalloc, which allocates nothing: a fixed
+// array in every GPU's memory that the library runs on (each device holds its
+// own copy at its own address until the process ends).  Host code never
+// passes this name to a kernel: it is a host-side stand-in, not a device
+// address.  The device address is looked up once per device
+// (static_scratch_address) and only that pointer is used.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on device `dev`, which must be the current
+// device; looked up on the first call for that device (esi_create_state),
+// then cached.  Null if the lookup fails.
+void* static_scratch_address(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_scratch[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+            g_static_scratch[dev] = p;
+        else
+            (void)hipGetLastError();
+    }
+    return g_static_scratch[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -161,22 +200,47 @@ bool device_accessible(const void* p)
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.isManaged;
 }
 
-// The scratch of one call under schedule sc (n events; nf_stage frame times
-// staged from host memory): frame times | table | segment sums | tile totals
-// | total | records, grown on demand (after the stream has finished with the
-// old one).
+// The scratch layout of one call under schedule sc (n events; nf_stage
+// frame times staged from host memory): frame times | table | segment sums |
+// tile totals | total | records.  Every part is written by the call's own
+// kernels before it is read (the tile totals are cleared by k_hist), so no
+// part needs clearing between calls.
+struct ScratchPlan {
+    size_t o_tab, o_bs, o_tt, o_tot, o_rec, need;
+};
+
+ScratchPlan scratch_plan(const Schedule& sc, int64_t n, int32_t nf_stage)
+{
+    ScratchPlan p{};
+    const int64_t M = n > 0 ? (int64_t)sc.ntiles * sc.nunits : 0;
+    const int64_t nseg = n > 0 ? (int64_t)scan_segments(sc.nunits) : 0;
+    p.o_tab = align_up(8 * (size_t)nf_stage, 256);
+    p.o_bs = p.o_tab + align_up(4 * (size_t)M, 256);
+    p.o_tt = p.o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
+    p.o_tot = p.o_tt + align_up(4 * (size_t)sc.ntiles, 256);
+    p.o_rec = p.o_tot + 256;
+    p.need = p.o_rec + 8 * (size_t)n;
+    return p;
+}
+
+void carve_scratch(char* base, const ScratchPlan& p, CallScratch& cs, int64_t** tf_stage)
+{
+    if (tf_stage)
+        *tf_stage = (int64_t*)base;
+    cs.table = (uint32_t*)(base + p.o_tab);
+    cs.blocksum = (uint32_t*)(base + p.o_bs);
+    cs.tile_tot = (uint32_t*)(base + p.o_tt);
+    cs.total = (uint32_t*)(base + p.o_tot);
+    cs.records = (uint64_t*)(base + p.o_rec);
+}
+
+// The state's own scratch for one call, grown on demand (after the stream
+// has finished with the old one).
 esi_status call_scratch(esi_state* st, const Schedule& sc, int64_t n, int32_t nf_stage,
                         hipStream_t stream, CallScratch& cs, int64_t** tf_stage)
 {
-    const int64_t M = n > 0 ? (int64_t)sc.ntiles * sc.nunits : 0;
-    const int64_t nseg = n > 0 ? (int64_t)scan_segments(sc.nunits) : 0;
-    const size_t o_tab = align_up(8 * (size_t)nf_stage, 256);
-    const size_t o_bs = o_tab + align_up(4 * (size_t)M, 256);
-    const size_t o_tt = o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
-    const size_t o_tot = o_tt + align_up(4 * (size_t)sc.ntiles, 256);
-    const size_t o_rec = o_tot + 256;
-    const size_t need = o_rec + 8 * (size_t)n;
-    if (need > st->scratch_bytes) {
+    const ScratchPlan p = scratch_plan(sc, n, nf_stage);
+    if (p.need > st->scratch_bytes) {
         // the old scratch may still be read by work queued on this stream
         if (st->scratch && hipStreamSynchronize(stream) != hipSuccess)
             return hip_fail(st);
@@ -184,21 +248,14 @@ esi_status call_scratch(esi_state* st, const Schedule& sc, int64_t n, int32_t nf
             (void)hipFree(st->scratch);
         st->scratch = nullptr;
         st->scratch_bytes = 0;
-        const size_t bytes = need + need / 4;
+        const size_t bytes = p.need + p.need / 4;
         if (hipMalloc(&st->scratch, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return ESI_ERR_OUT_OF_MEMORY;
         }
         st->scratch_bytes = bytes;
     }
-    char* base = (char*)st->scratch;
-    if (tf_stage)
-        *tf_stage = (int64_t*)base;
-    cs.table = (uint32_t*)(base + o_tab);
-    cs.blocksum = (uint32_t*)(base + o_bs);
-    cs.tile_tot = (uint32_t*)(base + o_tt);
-    cs.total = (uint32_t*)(base + o_tot);
-    cs.records = (uint64_t*)(base + o_rec);
+    carve_scratch((char*)st->scratch, p, cs, tf_stage);
     return ESI_OK;
 }
 
@@ -234,6 +291,9 @@ const char* esi_status_string(esi_status s)
         return "ESI_ERR_HIP: a HIP runtime call failed; the state is poisoned";
     case ESI_ERR_POISONED:
         return "ESI_ERR_POISONED: an earlier HIP failure; call esi_reset or esi_import_state";
+    case ESI_ERR_SCRATCH_LIMIT:
+        return "ESI_ERR_SCRATCH_LIMIT: the call needs more scratch than the static 64 MiB of "
+               "esi_integrate_window_noalloc";
     }
     return "ESI_ERR_UNKNOWN";
 }
@@ -280,6 +340,7 @@ esi_status esi_create_state(int32_t width, int32_t height, const esi_params* par
     st->diag = (DiagDev*)(base + o_diag);
     st->bucket_slots =
         bucket_slots(make_schedule(band_rows(width, height) * width, 0, 1).ntiles);
+    st->static_scratch = static_scratch_address(st->device);
     if (launch_reset(st->dev, params->t0_us, st->diag, stream) != hipSuccess) {
         (void)hipFree(st->state_mem);
         delete st;
@@ -367,9 +428,16 @@ esi_status esi_reset(esi_state* st, hipStream_t stream)
     return ESI_OK;
 }
 
-esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64_t* t_frames,
-                                int32_t n_frames, float* frames, uint8_t* frames_u8,
-                                hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+// One integrate call (esi_integrate_window, esi_integrate_window_noalloc):
+// argument checks, the schedule, scratch from the state's own buffer or from
+// the device's static array, and the launches of every band.
+esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int64_t* t_frames,
+                                 int32_t n_frames, float* frames, uint8_t* frames_u8,
+                                 hipStream_t stream, bool static_scratch)
 {
     if (!st || !ev || n_frames < 0)
         return ESI_ERR_INVALID_ARG;
@@ -396,7 +464,18 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
     const Schedule sc0 = make_schedule(rows * st->W, n, st->bucket_slots, st->min_ppt);
     CallScratch cs{};
     int64_t* tf_dev = nullptr;
-    if (n > 0 || stage_tf) {
+    if (static_scratch) {
+        // frame times must already be device memory (nothing is staged), and
+        // the call's scratch must fit the static array
+        if (stage_tf)
+            return ESI_ERR_INVALID_ARG;
+        const ScratchPlan p = scratch_plan(sc0, n, 0);
+        if (p.need > kStaticScratchBytes)
+            return ESI_ERR_SCRATCH_LIMIT;
+        if (!st->static_scratch)
+            return ESI_ERR_HIP;
+        carve_scratch((char*)st->static_scratch, p, cs, nullptr);
+    } else if (n > 0 || stage_tf) {
         const esi_status rc =
             call_scratch(st, sc0, n, stage_tf ? n_frames : 0, stream, cs, &tf_dev);
         if (rc != ESI_OK)
@@ -437,6 +516,24 @@ esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64
         return hip_fail(st);
     st->calls++;
     return ESI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+esi_status esi_integrate_window(esi_state* st, const esi_events* ev, const int64_t* t_frames,
+                                int32_t n_frames, float* frames, uint8_t* frames_u8,
+                                hipStream_t stream)
+{
+    return integrate_window_impl(st, ev, t_frames, n_frames, frames, frames_u8, stream, false);
+}
+
+esi_status esi_integrate_window_noalloc(esi_state* st, const esi_events* ev,
+                                        const int64_t* t_frames, int32_t n_frames, float* frames,
+                                        uint8_t* frames_u8, hipStream_t stream)
+{
+    return integrate_window_impl(st, ev, t_frames, n_frames, frames, frames_u8, stream, true);
 }
 
 esi_status esi_snapshot_frame(esi_state* st, int64_t t_frame_us, float* frame, uint8_t* u8,

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     import paper_2508_02238_amd as esi
-    for s in range(5):
+    for s in range(6):
         assert esi.esi_status_string(s).startswith("ESI_")
     assert "UNKNOWN" in esi.esi_status_string(99)
 

@@ -215,6 +215,16 @@ esi_status esi_get_diagnostics(esi_state *st, esi_diag *out);
  * smaller tiles give more workgroups (an autotuner picks it per workload). */
 esi_status esi_set_tile_pixels(esi_state *st, int32_t tile_pixels);
 
+/* Phase A's split between its two forms of the same recurrence (Alg. 2's
+ * event loop; the per-event maps composed as in Eq. (5)), for later calls on
+ * this state: within one chunk of a tile's events, a pixel's run of at most
+ * scan_run events is integrated by its own lane, one event after the other,
+ * and a longer run by its whole wave, 64 events at a time, as a scan of the
+ * per-event clamp-affine maps (hot pixels and same-time bursts).  scan_run
+ * >= 0, 0 for the default (64); e.g. INT32_MAX turns the scan off.  N, P and
+ * T do not depend on it, S and frames only to rounding. */
+esi_status esi_set_scan_run(esi_state *st, int32_t scan_run);
+
 /* Sensor size of a state. */
 esi_status esi_get_size(const esi_state *st, int32_t *width, int32_t *height);
 

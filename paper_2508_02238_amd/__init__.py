@@ -87,6 +87,7 @@ _SIGNATURES = [
                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_VP),
                                            ctypes.POINTER(_VP), _VP]),
     ("esi_set_tile_pixels", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("esi_set_scan_run", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("esi_status_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
@@ -159,6 +160,10 @@ def esi_integrate_window_noalloc(st, x_ptr, y_ptr, t_ptr, p_ptr, n, t_frames_ptr
 
 def esi_set_tile_pixels(st, tile_pixels: int) -> int:
     return lib.esi_set_tile_pixels(_VP(st), int(tile_pixels))
+
+
+def esi_set_scan_run(st, scan_run: int) -> int:
+    return lib.esi_set_scan_run(_VP(st), int(scan_run))
 
 
 def esi_batch_create(max_items: int):
@@ -354,6 +359,9 @@ class State:
 
     def set_tile_pixels(self, tile_pixels: int):
         _check(esi_set_tile_pixels(self.handle, tile_pixels), "esi_set_tile_pixels")
+
+    def set_scan_run(self, scan_run: int):
+        _check(esi_set_scan_run(self.handle, scan_run), "esi_set_scan_run")
 
     def diagnostics(self) -> dict:
         rc, d = esi_get_diagnostics(self.handle)

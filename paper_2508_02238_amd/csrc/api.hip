@@ -15,6 +15,12 @@
 
 using namespace esi;
 
+// A pixel's run of more than this many events in one chunk of its tile is
+// integrated by the scan of the whole wave rather than by one lane: below it
+// the wave's fixed cost per 64 events (the scan's six composition steps)
+// exceeds one lane's loop.
+constexpr int kDefaultScanRun = 64;
+
 struct esi_state {
     int32_t W = 0, H = 0;
     int64_t npix = 0;
@@ -32,6 +38,7 @@ struct esi_state {
     void* static_scratch = nullptr;
     int bucket_slots = 1024;  // bucketing workgroups resident at once
     int min_ppt = 1;          // smallest pixels per thread of the integration tiles
+    int scan_run = kDefaultScanRun;  // longer runs per chunk take the wave's scan
     bool state_in_range = true;  // every S in [s_min, s_max] (false after importing one outside)
     bool poisoned = false;
     uint64_t calls = 0;
@@ -117,9 +124,10 @@ bool params_ok(const esi_params* p)
            (p->flags & ~(uint32_t)(ESI_DECAY_THEN_ADD | ESI_SNAPSHOT_LAZY | ESI_DECAY_EXP)) == 0;
 }
 
-MethodParams method_params(const esi_params& p)
+MethodParams method_params(const esi_params& p, int scan_run)
 {
     MethodParams mp{};
+    mp.scan_run = scan_run;
     mp.C = p.C;
     mp.k = p.k_per_us;
     mp.b = p.b;
@@ -453,7 +461,7 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
         return ESI_ERR_POISONED;
     DeviceGuard g(st->device);
     const int64_t n = (int64_t)ev->n;
-    MethodParams mp = method_params(st->params);
+    MethodParams mp = method_params(st->params, st->scan_run);
     if (!st->state_in_range)
         mp.need_clamp = 1;
     // the sensor in bands of rows, one pass of the kernels each (one band
@@ -544,7 +552,7 @@ esi_status esi_snapshot_frame(esi_state* st, int64_t t_frame_us, float* frame, u
     if (st->poisoned)
         return ESI_ERR_POISONED;
     DeviceGuard g(st->device);
-    if (launch_snapshot(st->dev, method_params(st->params), t_frame_us, frame, u8, stream) !=
+    if (launch_snapshot(st->dev, method_params(st->params, st->scan_run), t_frame_us, frame, u8, stream) !=
         hipSuccess)
         return hip_fail(st);
     return ESI_OK;
@@ -672,6 +680,14 @@ esi_status esi_set_tile_pixels(esi_state* st, int32_t tile_pixels)
                  tile_pixels == 1024 || tile_pixels == 2048))
         return ESI_ERR_INVALID_ARG;
     st->min_ppt = tile_pixels ? tile_pixels / 256 : 1;
+    return ESI_OK;
+}
+
+esi_status esi_set_scan_run(esi_state* st, int32_t scan_run)
+{
+    if (!st || scan_run < 0)
+        return ESI_ERR_INVALID_ARG;
+    st->scan_run = scan_run ? scan_run : kDefaultScanRun;
     return ESI_OK;
 }
 
@@ -827,7 +843,7 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         x = BatchItem{};
         x.ev = EventsDev{events[i].x, events[i].y, events[i].t, events[i].p, n, 0, st->H};
         x.st = st->dev;
-        x.mp = method_params(st->params);
+        x.mp = method_params(st->params, st->scan_run);
         if (!st->state_in_range)
             x.mp.need_clamp = 1;
         const int32_t nf = n_frames ? n_frames[i] : 0;

@@ -27,6 +27,9 @@ struct MethodParams {
     int lazy;
     int exp_decay;   // d = exp(-k dt) instead of Eq. (4)
     int need_clamp;  // a decayed state can leave [s_min, s_max]
+    // a pixel's run of more than scan_run events in one chunk goes through
+    // the wave's scan of its per-event maps instead of one lane's loop
+    int scan_run;
 };
 
 // How the decay is evaluated: Eq. (4), d = max(1 - k dt, 0)^b, with b = 1 and
@@ -129,6 +132,92 @@ __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+}
+
+// ---- the per-event map of Alg. 2 and its composition ------------------------
+//
+// One event of a pixel maps the state S to clamp(a S + b, lo, hi) (Eq. (13)'s
+// clamp after the add and the decay of Alg. 1/2): add then decay gives
+// a = d, b = d p C; decay then add gives a = d, b = p C; lo, hi = S_min, S_max.
+// With a >= 0 these maps are closed under composition (Eq. (5) unrolls the
+// same recurrence into products of decay factors):
+//   (g after f)(x) = clamp(g.a f.a x + g.a f.b + g.b, L, H),
+//   L = clamp(g.a f.lo + g.b, g.lo, g.hi),  H = clamp(g.a f.hi + g.b, g.lo, g.hi),
+// because x -> g.a x + g.b is non-decreasing and a clamp of a clamp is the
+// clamp to the clamped bounds.  Composition is associative, so the states
+// after every event of a run are an inclusive scan of its maps.
+struct ClampAffine {
+    double a, b, lo, hi;
+};
+
+__device__ __forceinline__ ClampAffine clamp_affine_identity()
+{
+    return ClampAffine{1.0, 0.0, -1.7976931348623157e308, 1.7976931348623157e308};
+}
+
+// g after f.
+__device__ __forceinline__ ClampAffine compose(const ClampAffine& f, const ClampAffine& g)
+{
+    ClampAffine r;
+    r.a = g.a * f.a;
+    r.b = __fma_rn(g.a, f.b, g.b);
+    r.lo = fmin(fmax(__fma_rn(g.a, f.lo, g.b), g.lo), g.hi);
+    r.hi = fmin(fmax(__fma_rn(g.a, f.hi, g.b), g.lo), g.hi);
+    return r;
+}
+
+__device__ __forceinline__ double apply(const ClampAffine& f, double x)
+{
+    return fmin(fmax(__fma_rn(f.a, x, f.b), f.lo), f.hi);
+}
+
+// A double moved across lanes by a DPP control (two 32-bit moves); lanes the
+// control gives no source (or that ROW_MASK leaves out) take `old`.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double old, double src)
+{
+    const long long o = __double_as_longlong(old), s = __double_as_longlong(src);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), CTRL, ROW_MASK,
+                                               0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void scan_step(ClampAffine& m)
+{
+    const ClampAffine id = clamp_affine_identity();
+    ClampAffine p;
+    p.a = dpp_f64<CTRL, ROW_MASK>(id.a, m.a);
+    p.b = dpp_f64<CTRL, ROW_MASK>(id.b, m.b);
+    p.lo = dpp_f64<CTRL, ROW_MASK>(id.lo, m.lo);
+    p.hi = dpp_f64<CTRL, ROW_MASK>(id.hi, m.hi);
+    m = compose(p, m);  // the earlier lanes' map first
+}
+
+// Inclusive scan of the lanes' maps in lane order: lane l returns map_l after
+// ... after map_0.  Rows of 16 lanes first (shifts by 1, 2, 4, 8), then row
+// 0's total into row 1 and row 2's into row 3 (row_bcast:15), then rows 0-1's
+// total into rows 2 and 3 (row_bcast:31).  Lanes without a source compose
+// the identity.
+__device__ __forceinline__ ClampAffine wave_scan(ClampAffine m)
+{
+    scan_step<0x111, 0xF>(m);  // row_shr:1
+    scan_step<0x112, 0xF>(m);  // row_shr:2
+    scan_step<0x114, 0xF>(m);  // row_shr:4
+    scan_step<0x118, 0xF>(m);  // row_shr:8
+    scan_step<0x142, 0xA>(m);  // row_bcast:15 into rows 1 and 3
+    scan_step<0x143, 0xC>(m);  // row_bcast:31 into rows 2 and 3
+    return m;
+}
+
+// Lane l's double, read by the whole wave (l uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFF), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // Stable multisplit rank inside one wave step.  Lane l holds an element with

@@ -19,7 +19,11 @@
 //   3. phase A: each thread runs the events of its pixels through Alg. 2 in
 //      array order and records a change list: for every frame of the segment
 //      at which the pixel's visible state changes, the frame index and the
-//      state after the last event that frame includes;
+//      state after the last event that frame includes.  A pixel's run of more
+//      than scan_run events (hot pixels, same-time bursts) is left to its
+//      whole wave instead, which composes the run's per-event clamp-affine
+//      maps with a DPP scan, 64 events at a time (3b), so that one long run
+//      does not hold the other 63 lanes;
 //   4. phase B: the segment's frames, every thread writing its pixels' values
 //      (Eq. (14)); a frame compares its index with the pixel's next change
 //      and only lanes with a change touch LDS.
@@ -124,15 +128,6 @@ __device__ __forceinline__ void take_change(Pixels<PPT>& px, int i, const double
     px.jo[i] += 2u;
 }
 
-// A lane's double, read by the whole wave (l uniform).
-__device__ __forceinline__ double lane_value(double v, int l)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFF), l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 // Buffer resource for one frame row piece of `bytes` bytes: stores at or past
 // `bytes` (pixel slots off the sensor in the last tile) are dropped by the
 // buffer range check.  Word 3 is the gfx9 raw-buffer format.
@@ -203,7 +198,7 @@ __device__ __forceinline__ void walk_frames(const MethodParams& mp, Pixels<PPT>&
                                             int64_t npix, uint32_t fbytes, uint32_t ubytes)
 {
     for (int jj = jj0; jj < jj1; ++jj) {
-        const double kt = LAZY ? 0.0 : lane_value(ktv, jj - jj0);
+        const double kt = LAZY ? 0.0 : readlane_f64(ktv, jj - jj0);
         const __amdgpu_buffer_rsrc_t fr = row_rsrc((OUT & 1) ? (void*)frow : nullptr, fbytes);
         const __amdgpu_buffer_rsrc_t ur = row_rsrc((OUT & 2) ? (void*)urow : nullptr, ubytes);
         frame_step<PPT, NB, BK, LAZY, CLAMP, OUT>(mp, px, jj, kt, chg_S, chg_A, chg_j, fr, ur);
@@ -584,13 +579,23 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
             // clamp bounds in canonical form once, not on every event
             const double s_min = __builtin_canonicalize(mp.s_min);
             const double s_max = __builtin_canonicalize(mp.s_max);
+            // runs longer than mp.scan_run are left to the wave's scan (3b)
+            uint32_t begs[PPT], ends[PPT];
+            double A0s[PPT];
+            bool lng[PPT];
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 const int l = tid + i * NB;
                 const uint32_t end = min((l + 1 < TILE) ? (uint32_t)cnt[0][l + 1] : cn, cn);
                 const uint32_t beg = min((uint32_t)cnt[0][l], end);
+                begs[i] = beg;
+                ends[i] = end;
+                A0s[i] = __fma_rn(mp.k, (double)(px.T[i] - c.t_first), 1.0);
+                lng[i] = end - beg > (uint32_t)mp.scan_run;
+                if (lng[i])
+                    continue;
                 double S = px.S[i];
-                double A = __fma_rn(mp.k, (double)(px.T[i] - c.t_first), 1.0);
+                double A = A0s[i];
                 uint32_t w = beg, nneg = 0;
                 int jc_prev = nfw;  // frame of the events applied so far (nfw: none)
                 auto run = [&](auto decay_then_add) {
@@ -645,6 +650,89 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
                 px.jn[i] = chg_j[beg + (uint32_t)l];
                 px.eo[i] = 8u * beg;
                 px.jo[i] = 2u * (beg + (uint32_t)l + 1u);
+            }
+
+            // 3b. each run longer than mp.scan_run, one after the other, by
+            // the whole wave of its pixel: blocks of 64 events, lane e taking
+            // event b0 + e.  Every lane builds its event's map (the decay
+            // from the previous event's time, lane e - 1's kt, or the pixel's
+            // A for the run's first event), the wave scans the maps
+            // (wave_scan), and lane e applies the composed map to the state
+            // before the block, which gives the state after its event.  The
+            // change-list entries are the events whose next event belongs to
+            // a later frame (or that end the run), at positions counted with
+            // a ballot; they land at or before their own event, behind every
+            // read of the block, and the next block only reads later events.
+            auto scan_run = [&](auto decay_then_add, int i, int owner) {
+                const uint32_t beg = (uint32_t)__builtin_amdgcn_readlane((int)begs[i], owner);
+                const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int)ends[i], owner);
+                const uint32_t l = (uint32_t)(tid - lane + owner + i * NB);
+                double S = readlane_f64(px.S[i], owner);
+                double A = readlane_f64(A0s[i], owner);
+                // the run's last event, read before any entry can overwrite it
+                const int64_t t_last = t_ref + record_dt(sorted[end - 1]);
+                uint32_t w = beg, nneg = 0;
+                for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
+                    const uint32_t e = b0 + (uint32_t)lane;
+                    const bool valid = e < end;
+                    const bool has_next = e + 1u < end;
+                    const double kt = ktvs[valid ? e : b0];
+                    const double kt_n = ktvs[has_next ? e + 1u : b0];
+                    const uint32_t low = (uint32_t)__double_as_longlong(kt);
+                    const int jc = (int)(low & 0x7Fu);
+                    const uint32_t neg = (low >> 7) & 1u;
+                    const int jc_n = has_next ? (int)((uint32_t)__double_as_longlong(kt_n) & 0x7Fu) : -1;
+                    // the previous event's kt (wave_shr:1); lane 0 takes A
+                    const double kt_p = dpp_f64<0x138>(0.0, kt);
+                    const double A_p = (lane == 0) ? A : 1.0 + kt_p;
+                    const double d = decay_from_base<BK>(A_p - kt, mp.b);
+                    const double sc = __hiloint2double((int)(c_hi + (neg << 31)), (int)c_lo);
+                    ClampAffine f = clamp_affine_identity();
+                    if (valid) {
+                        f.a = d;
+                        f.b = decltype(decay_then_add)::value ? sc : d * sc;
+                        f.lo = s_min;
+                        f.hi = s_max;
+                    }
+                    f = wave_scan(f);
+                    const double S_e = apply(f, S);
+                    const bool ge = valid && jc < nfw && jc_n != jc;
+                    const uint64_t gm = __ballot(ge);
+                    if (ge) {
+                        const uint32_t at = w + (uint32_t)__popcll(gm & ((1ull << lane) - 1ull));
+                        const double A_e = 1.0 + kt;
+                        chg_S[at] = S_e * mp.inv_range;
+                        chg_A[at] = (BK == kDecayExp) ? exp(A_e + dA - 1.0) : A_e + dA;
+                        chg_j[at + l] = (uint16_t)jc;
+                    }
+                    const int last = (int)min(end - b0, (uint32_t)kWave) - 1;
+                    S = readlane_f64(S_e, last);
+                    A = 1.0 + readlane_f64(kt, last);
+                    w += (uint32_t)__popcll(gm);
+                    nneg += (uint32_t)__popcll(__ballot(valid && neg != 0u));
+                }
+                if (lane == owner) {
+                    px.S[i] = S;
+                    px.T[i] = t_last;
+                    px.N[i] += end - beg;
+                    px.P[i] += (int32_t)(end - beg) - 2 * (int32_t)nneg;
+                    chg_j[w + l] = 0xFFFF;
+                    px.jn[i] = chg_j[beg + l];
+                    px.eo[i] = 8u * beg;
+                    px.jo[i] = 2u * (beg + l + 1u);
+                }
+            };
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                uint64_t todo = __ballot(lng[i]);
+                while (todo) {
+                    const int owner = (int)__builtin_ctzll(todo);
+                    todo &= todo - 1ull;
+                    if (mp.decay_then_add)
+                        scan_run(std::true_type{}, i, owner);
+                    else
+                        scan_run(std::false_type{}, i, owner);
+                }
             }
         } else {
 #pragma unroll

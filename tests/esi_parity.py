@@ -20,15 +20,18 @@ REL = 1e-5
 
 
 def gpu_run(esi, stream, prm: dict, t_frames=None, calls=None, want_u8=False,
-            frame_sel=None):
+            frame_sel=None, scan_run=None):
     """Integrate on the GPU through the C ABI binding.  calls: list of
     (lo, hi) event ranges, one esi_integrate_window call each (default: one
     call).  A frame goes to the call after whose events it is complete: the
     first call c such that t_frames[j] < first time of call c+1 (the last
     call takes the rest).  Returns frames (rows frame_sel if given), u8,
-    state (S, T, N, P) and the diagnostics."""
+    state (S, T, N, P) and the diagnostics.  scan_run: the state's
+    serial-versus-scan run length (None: the library's default)."""
     import torch
     st = esi.State(stream.width, stream.height, **prm)
+    if scan_run is not None:
+        st.set_scan_run(scan_run)
     n = stream.n
     tf = None if t_frames is None else np.asarray(t_frames, np.int64)
     calls = calls or [(0, n)]

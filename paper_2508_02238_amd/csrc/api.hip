@@ -37,6 +37,7 @@ struct esi_state {
     // the lookup failed: esi_integrate_window_noalloc then returns ESI_ERR_HIP)
     void* static_scratch = nullptr;
     int bucket_slots = 1024;  // bucketing workgroups resident at once
+    int integ_slots[4] = {1 << 30, 1 << 30, 1 << 30, 1 << 30};  // per ppt 1, 2, 4, 8
     int min_ppt = 1;          // smallest pixels per thread of the integration tiles
     int scan_run = kDefaultScanRun;  // longer runs per chunk take the wave's scan
     bool state_in_range = true;  // every S in [s_min, s_max] (false after importing one outside)
@@ -149,7 +150,8 @@ MethodParams method_params(const esi_params& p, int scan_run)
 // The split of one call into tiles and bucketing units: the smallest tile
 // (most workgroups) with at most kMaxTiles tiles; the events split evenly over
 // as many bucketing workgroups as the GPU holds at once (`slots`).
-Schedule make_schedule(int64_t npix, int64_t n, int slots, int min_ppt = 1)
+Schedule make_schedule(int64_t npix, int64_t n, int slots, int min_ppt = 1,
+                       const int* integ_slots = nullptr)
 {
     Schedule s{};
     for (int ppt = min_ppt; ppt <= 8; ppt *= 2) {
@@ -159,6 +161,8 @@ Schedule make_schedule(int64_t npix, int64_t n, int slots, int min_ppt = 1)
         if (s.ntiles <= kMaxTiles)
             break;
     }
+    const int pi = s.ppt == 1 ? 0 : s.ppt == 2 ? 1 : s.ppt == 4 ? 2 : 3;
+    s.ordered = n > 0 && integ_slots && s.ntiles > integ_slots[pi];
     const int64_t per = (n + slots - 1) / std::max(slots, 1);
     s.unit_events = std::max<int64_t>(256, (per + 255) / 256 * 256);
     s.nunits = (n + s.unit_events - 1) / s.unit_events;
@@ -210,11 +214,11 @@ bool device_accessible(const void* p)
 
 // The scratch layout of one call under schedule sc (n events; nf_stage
 // frame times staged from host memory): frame times | table | segment sums |
-// tile totals | total | records.  Every part is written by the call's own
+// tile totals | tile order | total | records.  Every part is written by the call's own
 // kernels before it is read (the tile totals are cleared by k_hist), so no
 // part needs clearing between calls.
 struct ScratchPlan {
-    size_t o_tab, o_bs, o_tt, o_tot, o_rec, need;
+    size_t o_tab, o_bs, o_tt, o_ord, o_tot, o_rec, need;
 };
 
 ScratchPlan scratch_plan(const Schedule& sc, int64_t n, int32_t nf_stage)
@@ -225,9 +229,12 @@ ScratchPlan scratch_plan(const Schedule& sc, int64_t n, int32_t nf_stage)
     p.o_tab = align_up(8 * (size_t)nf_stage, 256);
     p.o_bs = p.o_tab + align_up(4 * (size_t)M, 256);
     p.o_tt = p.o_bs + align_up(4 * (size_t)(nseg * sc.ntiles), 256);
-    p.o_tot = p.o_tt + align_up(4 * (size_t)sc.ntiles, 256);
+    p.o_ord = p.o_tt + align_up(4 * (size_t)sc.ntiles, 256);
+    p.o_tot = p.o_ord + align_up(4 * (size_t)sc.ntiles, 256);
     p.o_rec = p.o_tot + 256;
-    p.need = p.o_rec + 8 * (size_t)n;
+    // records: n, and one spare slot that the bucketing writes for lanes
+    // without a record
+    p.need = p.o_rec + 8 * ((size_t)n + 1);
     return p;
 }
 
@@ -238,6 +245,7 @@ void carve_scratch(char* base, const ScratchPlan& p, CallScratch& cs, int64_t** 
     cs.table = (uint32_t*)(base + p.o_tab);
     cs.blocksum = (uint32_t*)(base + p.o_bs);
     cs.tile_tot = (uint32_t*)(base + p.o_tt);
+    cs.order = (uint32_t*)(base + p.o_ord);
     cs.total = (uint32_t*)(base + p.o_tot);
     cs.records = (uint64_t*)(base + p.o_rec);
 }
@@ -349,6 +357,8 @@ esi_status esi_create_state(int32_t width, int32_t height, const esi_params* par
     st->bucket_slots =
         bucket_slots(make_schedule(band_rows(width, height) * width, 0, 1).ntiles);
     st->static_scratch = static_scratch_address(st->device);
+    for (int i = 0; i < 4; ++i)
+        st->integ_slots[i] = integrate_slots(1 << i);
     if (launch_reset(st->dev, params->t0_us, st->diag, stream) != hipSuccess) {
         (void)hipFree(st->state_mem);
         delete st;
@@ -505,7 +515,8 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
     for (int64_t y0 = 0; y0 < st->H; y0 += rows) {
         const int64_t hb = std::min<int64_t>(rows, st->H - y0);
         const StateDev sd = band_state(st->dev, y0, hb);
-        const Schedule sc = make_schedule(sd.npix, n, st->bucket_slots, st->min_ppt);
+        const Schedule sc =
+            make_schedule(sd.npix, n, st->bucket_slots, st->min_ppt, st->integ_slots);
         const EventsDev evd{ev->x, ev->y, ev->t, ev->p, n, (int)y0, st->H};
         const int64_t off = y0 * st->W;
         const FrameOut fo{tf, n_frames, frames ? frames + off : nullptr,

@@ -264,62 +264,74 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
     uint32_t flags = 0;
     bool bad = false;
 
+    // The sub-batches are software-pipelined: the first half of the next
+    // sub-batch's events is loaded before this sub-batch's records are
+    // written and the second half before the first is ranked, and the record
+    // stores are a fixed sequence with no branch (a lane without a record
+    // writes the spare slot records[cap]), so that the wait for a half leaves
+    // the stores issued after it in flight: on CDNA one counter tracks vector
+    // loads and stores, and a variable number of stores would make the
+    // compiler wait for all of them.
+    const int w0 = wave * PER_WAVE;
+    constexpr int HALF = STEPS / 2;
+    static_assert(STEPS % 2 == 0, "two halves of a sub-batch");
+    uint32_t xs[STEPS], ys[STEPS];
+    int64_t ts[STEPS];
+    int ps[STEPS];
+    int64_t tc = INT64_MIN;  // time of the event before this wave's first one
+    // loads of steps [s0, s0 + HALF) of the sub-batch at sb: offsets clamped
+    // into [u_lo, u_hi), so every load is valid and none depends on a select
+    // of loaded values
+    auto load_half = [&](int64_t sb, int s0) {
+#pragma unroll
+        for (int st = s0; st < s0 + HALF; ++st) {
+            const int64_t o = min(sb + (int64_t)(w0 + st * kWave + lane), u_hi - 1);
+            xs[st] = ev.x[o];
+            ys[st] = ev.y[o];
+            ts[st] = ev.t[o];
+            ps[st] = ev.p[o];
+        }
+        if (s0 == 0)
+            tc = ev.t[max(min(sb + (int64_t)w0, u_hi) - 1, (int64_t)0)];
+    };
+    if (u_lo < u_hi)
+        load_half(u_lo, 0);
+
     for (int64_t sb = u_lo; sb < u_hi; sb += SUB) {
         // this sub-batch's events: [sb, sb + nsb); this wave's: from sb + w0
         const int nsb = (int)min((int64_t)SUB, u_hi - sb);
-        const int w0 = wave * PER_WAVE;
-        const uint16_t* xb = ev.x + sb;
-        const uint16_t* yb = ev.y + sb;
-        const int64_t* tb = ev.t + sb;
-        const int8_t* pb = ev.p + sb;
-        int64_t t_carry = (sb + w0 > 0 && w0 < nsb) ? ev.t[sb + w0 - 1] : INT64_MIN;
+        load_half(sb, HALF);
+        int64_t t_carry = (sb + w0 > 0 && w0 < nsb) ? tc : INT64_MIN;
         uint64_t recs[STEPS];
         uint32_t packed[STEPS];  // rank | tile << 16, or ~0 for no event
 #pragma unroll
-        for (int b0 = 0; b0 < STEPS; b0 += BATCH) {
-            uint32_t xs[BATCH], ys[BATCH];
-            int64_t ts[BATCH];
-            int ps[BATCH];
-#pragma unroll
-            for (int s = 0; s < BATCH; ++s) {
-                // clamped 32-bit offset, no select on the loaded values: all
-                // loads of the batch stay in flight together
-                const int o = min(w0 + (b0 + s) * kWave + lane, nsb - 1);
-                xs[s] = xb[o];
-                ys[s] = yb[o];
-                ts[s] = tb[o];
-                ps[s] = pb[o];
-            }
-#pragma unroll
-            for (int s = 0; s < BATCH; ++s) {
-                const bool in = w0 + (b0 + s) * kWave + lane < nsb;
-                const uint32_t yl = ys[s] - (uint32_t)ev.y0;
-                const uint32_t q = yl * (uint32_t)W + xs[s];
-                const bool ok = in && xs[s] < (uint32_t)W && yl < (uint32_t)H;
-                const int64_t t = ts[s];
-                // decreasing time versus the previous event in array order:
-                // the previous lane's time (lane 0: the previous step's last)
-                const uint64_t tu = (uint64_t)t, cu = (uint64_t)t_carry;
-                const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(
-                    (int)(uint32_t)cu, (int)(uint32_t)tu, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
-                const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(
-                    (int)(uint32_t)(cu >> 32), (int)(uint32_t)(tu >> 32), 0x138, 0xF, 0xF, false);
-                const int64_t tprev = (int64_t)(((uint64_t)phi << 32) | plo);
-                if (in && t < tprev)
-                    flags |= 1u;  // ESI_DIAG_UNSORTED
-                t_carry = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(tu >> 32), kWave - 1) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)tu, kWave - 1));
-                const int64_t dt = t - t_ref;
-                if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
-                    flags |= 4u;  // ESI_DIAG_TIME_RANGE
-                const uint32_t key = ok ? (q >> tile_log) : 0u;
-                const uint32_t rank = wave_stable_rank_or<kWavesPerBlock>(ok, key, mycw, myrep, mygroup);
-                packed[b0 + s] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
-                recs[b0 + s] = pack_record(dt, q & tmask, ps[s] > 0);
-            }
+        for (int st = 0; st < STEPS; ++st) {
+            const bool in = w0 + st * kWave + lane < nsb;
+            const uint32_t yl = ys[st] - (uint32_t)ev.y0;
+            const uint32_t q = yl * (uint32_t)W + xs[st];
+            const bool ok = in && xs[st] < (uint32_t)W && yl < (uint32_t)H;
+            const int64_t t = ts[st];
+            // decreasing time versus the previous event in array order:
+            // the previous lane's time (lane 0: the previous step's last)
+            const uint64_t tu = (uint64_t)t, cu = (uint64_t)t_carry;
+            const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(
+                (int)(uint32_t)cu, (int)(uint32_t)tu, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+            const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(
+                (int)(uint32_t)(cu >> 32), (int)(uint32_t)(tu >> 32), 0x138, 0xF, 0xF, false);
+            const int64_t tprev = (int64_t)(((uint64_t)phi << 32) | plo);
+            if (in && t < tprev)
+                flags |= 1u;  // ESI_DIAG_UNSORTED
+            t_carry = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(tu >> 32), kWave - 1) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)tu, kWave - 1));
+            const int64_t dt = t - t_ref;
+            if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
+                flags |= 4u;  // ESI_DIAG_TIME_RANGE
+            const uint32_t key = ok ? (q >> tile_log) : 0u;
+            const uint32_t rank = wave_stable_rank_or<kWavesPerBlock>(ok, key, mycw, myrep, mygroup);
+            packed[st] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
+            recs[st] = pack_record(dt, q & tmask, ps[st] > 0);
         }
         __syncthreads();
-
         // exclusive scan over (tile, wave), tile-major: start of each wave's
         // run of each tile inside the sub-batch sorted by tile; each tile's
         // bucket position advances by its count here, and wd keeps the
@@ -387,17 +399,22 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
         }
         __syncthreads();
 
+        // the first half of the next sub-batch's events, in flight during
+        // the write-back
+        load_half(sb + SUB, 0);
+
         // each tile's run of this sub-batch is appended to its bucket:
         // consecutive staged records of one tile land on consecutive
         // addresses; the counters are cleared for the next sub-batch
         const uint32_t total = min(sub_total, (uint32_t)SUB);
-        for (uint32_t p = tid; p < total; p += kBlock) {
+#pragma unroll
+        for (int i = 0; i < SUB / kBlock; ++i) {
+            const uint32_t p = (uint32_t)(tid + i * kBlock);
             const uint32_t k = skey[p];
-            const int64_t g = (k < (uint32_t)K) ? (int64_t)(uint32_t)(wd[k] + p) : -1;
-            if (g >= 0 && g < cap)
-                records[g] = staged[p];
-            else
-                bad = true;
+            const int64_t g = (p < total && k < (uint32_t)K) ? (int64_t)(uint32_t)(wd[k] + p) : -1;
+            const bool store = g >= 0 && g < cap;
+            bad |= p < total && !store;
+            records[store ? g : cap] = staged[p];
         }
         for (int k = tid; k < K; k += kBlock)
             cw[k] = 0;
@@ -449,6 +466,63 @@ __global__ __launch_bounds__(kBlock, 2) void k_bucket(EventsDev ev, int W, int H
 {
     bucket_body<SUB>(ev, W, H, tile_log, K, E, table, records, cap, diag,
                      xcd_block(blockIdx.x, gridDim.x));
+}
+
+// ---- integration order: tiles by event count, largest first -----------------
+// The integration launch has more tiles than the GPU holds workgroups, and
+// the tiles' event counts differ by an order of magnitude (a scene's moving
+// edges cross some tiles far more often than others).  Workgroups start in
+// index order, so listing the tiles largest first lets the short ones fill
+// the end of the launch (longest-processing-time-first list scheduling).
+// The tiles are sorted by a size class of their count (leading bit and four
+// bits after it); order within a class is whatever the LDS atomics give, a
+// schedule only: every tile's result is the same wherever it runs.
+constexpr int kOrderBlock = 1024;
+constexpr int kOrderClasses = 513;  // 0 for an empty tile, 1 + 16 e + m otherwise
+
+__device__ __forceinline__ uint32_t size_class(uint32_t c)
+{
+    if (c == 0)
+        return 0;
+    const int e = 31 - __clz(c);
+    const uint32_t m = (e >= 4 ? c >> (e - 4) : c << (4 - e)) & 15u;
+    return 1u + 16u * (uint32_t)e + m;
+}
+
+__global__ __launch_bounds__(kOrderBlock) void k_order(const uint32_t* tile_tot, int K,
+                                                       uint32_t* order)
+{
+    static_assert(kOrderClasses <= kOrderBlock, "one class per thread");
+    __shared__ uint32_t pos[kOrderBlock];
+    __shared__ uint32_t wsum[kOrderBlock / kWave];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    pos[tid] = 0;
+    __syncthreads();
+    // slot kOrderClasses - 1 - class: the largest class first
+    for (int k = tid; k < K; k += kOrderBlock)
+        atomicAdd(&pos[kOrderClasses - 1 - size_class(tile_tot[k])], 1u);
+    __syncthreads();
+    const uint32_t v = pos[tid];
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
+        if (lane >= o)
+            inc += n;
+    }
+    if (lane == kWave - 1)
+        wsum[wave] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w)
+        base += wsum[w];
+    pos[tid] = base + inc - v;  // exclusive start of this slot
+    __syncthreads();
+    for (int k = tid; k < K; k += kOrderBlock) {
+        const uint32_t at = atomicAdd(&pos[kOrderClasses - 1 - size_class(tile_tot[k])], 1u);
+        if (at < (uint32_t)K)
+            order[at] = (uint32_t)k;
+    }
 }
 
 // ---- batched calls: many streams per launch ---------------------------------
@@ -561,6 +635,9 @@ hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule
                        cs.tile_tot);
     hipLaunchKernelGGL(k_seg_down, grid, dim3(kBlock), 0, stream, cs.table, K, B, cs.blocksum,
                        cs.tile_tot, cs.total, diag);
+    if (sc.ordered)
+        hipLaunchKernelGGL(k_order, dim3(1), dim3(kOrderBlock), 0, stream, cs.tile_tot, K,
+                           cs.order);
     hipLaunchKernelGGL(k_bucket<kSub>, dim3((unsigned)B), dim3(kBlock), bucket_lds(K), stream, ev,
                        st.W, st.H, sc.tile_log, K, sc.unit_events, cs.table, cs.records, ev.n, diag);
     return hipGetLastError();

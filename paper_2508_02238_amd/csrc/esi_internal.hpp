@@ -19,6 +19,9 @@ struct Schedule {
     int ntiles;           // K = ceil(P / tile)
     int64_t unit_events;  // E
     int64_t nunits;       // B = ceil(n / E)
+    // the integration launch takes the tiles largest first (more tiles than
+    // the GPU holds integration workgroups at once)
+    bool ordered;
 };
 
 constexpr int kMaxTiles = 2000;  // bucketing LDS (staging + counters) stays near 32 KB
@@ -36,7 +39,8 @@ struct CallScratch {
     uint32_t* blocksum;   // [nseg][K]: per-segment sums
     uint32_t* tile_tot;   // [K]: events per tile
     uint32_t* total;      // [1]: number of accepted events
-    uint64_t* records;    // [n]
+    uint64_t* records;    // [n + 1]: the last a spare slot
+    uint32_t* order;      // [K]: tiles by size class of their event count, largest first
 };
 
 // Events of one call.  A sensor larger than one pass of the kernels holds is
@@ -101,6 +105,8 @@ struct BatchDev {
 
 // Bucketing workgroups the current device holds at once for K tiles.
 int bucket_slots(int K);
+// integration workgroups of `ppt` pixels per thread resident at once
+int integrate_slots(int ppt);
 // Segments of the column-wise table scan for B units.
 size_t scan_segments(int64_t B);
 

@@ -788,14 +788,18 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
     }
 }
 
-// One workgroup per tile of one call.
+// One workgroup per tile of one call.  Workgroups start in index order, so
+// with `order` (the tiles by event count, largest first) the longest tiles
+// start first and the short ones fill the end of the launch.
 template <int PPT, int NB, int BK>
 __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrate(
     const uint64_t* __restrict__ records, const uint32_t* __restrict__ table,
-    const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t, int K, StateDev st,
-    MethodParams mp, FrameOut fo, DiagDev* diag)
+    const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t,
+    const uint32_t* __restrict__ order, int K, StateDev st, MethodParams mp, FrameOut fo,
+    DiagDev* diag)
 {
-    integrate_body<PPT, NB, BK>(records, table, total, ev_t, K, st, mp, fo, diag, blockIdx.x);
+    const int tile = order ? (int)load_const(order, blockIdx.x) : (int)blockIdx.x;
+    integrate_body<PPT, NB, BK>(records, table, total, ev_t, K, st, mp, fo, diag, tile);
 }
 
 // Batched: the tiles of items [i0, i1) (one tile size and decay kind), work
@@ -876,7 +880,9 @@ hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Sch
     const bool has = ev.n > 0;
     hipLaunchKernelGGL((k_integrate<PPT, NB, BK>), dim3(sc.ntiles), dim3(NB), 0, stream,
                        has ? cs.records : nullptr, has ? cs.table : nullptr,
-                       has ? cs.total : nullptr, has ? ev.t : nullptr, sc.ntiles, st, mp, fo, diag);
+                       has ? cs.total : nullptr, has ? ev.t : nullptr,
+                       (has && sc.ordered) ? cs.order : nullptr,
+                       sc.ntiles, st, mp, fo, diag);
     return hipGetLastError();
 }
 
@@ -898,6 +904,34 @@ hipError_t launch_integrate_p(const EventsDev& ev, const StateDev& st, const Sch
 }
 
 }  // namespace
+
+int integrate_slots(int ppt)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) {
+        switch (ppt) {
+        case 1:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<1, 256, kDecayB2>, 256, 0);
+            break;
+        case 2:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<2, 256, kDecayB2>, 256, 0);
+            break;
+        case 4:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<4, 256, kDecayB2>, 256, 0);
+            break;
+        default:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<8, 256, kDecayB2>, 256, 0);
+        }
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1 << 30;  // unknown: never ordered
+    }
+    return std::max(1, cus) * std::max(1, per_cu);
+}
 
 int decay_kind(const MethodParams& mp)
 {

@@ -220,18 +220,21 @@ _BATCH_SCENES = {
 }
 
 
-def preset_batch(name: str = "c4", duration_us: int = 200_000, n_streams: int = 64,
+def preset_batch(name: str = "c4", duration_us: int = 200_000, n_streams: int | None = None,
                  threads: int | None = None) -> list[Stream]:
-    """The batched workload: n_streams independent streams, resolution drawn
-    uniformly from 346x260, 640x480 and 1280x720, event rate lognormal with
-    median 1.41 Mevents/s and sigma 1.03 (0.1 and 20 Mevents/s at the 0.5%
-    and 99.5% points), clipped to [0.1, 20] Mevents/s; each stream is the
-    scene of the single-stream workload of its size with its speed scaled to
-    the drawn rate (not re-tuned: rates land near the target).  Stream s uses
-    seed 4000 + s (workload 4)."""
-    if name != "c4":
+    """The batched and served workloads: independent streams, resolution
+    drawn uniformly from 346x260, 640x480 and 1280x720, event rate lognormal
+    with median 1.41 Mevents/s and sigma 1.03 (0.1 and 20 Mevents/s at the
+    0.5% and 99.5% points), clipped to [0.1, 20] Mevents/s; each stream is
+    the scene of the single-stream workload of its size with its speed scaled
+    to the drawn rate (not re-tuned: rates land near the target).  c4: 64
+    streams, stream s with seed 4000 + s; c5: 256 sessions, seed 5000 + s."""
+    if name not in ("c4", "c5"):
         raise KeyError(name)
-    rng = np.random.default_rng(4)
+    wl = 4 if name == "c4" else 5
+    if n_streams is None:
+        n_streams = 64 if wl == 4 else 256
+    rng = np.random.default_rng(wl)
     sizes = list(_BATCH_SCENES)
     out = []
     for s in range(n_streams):
@@ -243,7 +246,7 @@ def preset_batch(name: str = "c4", duration_us: int = 200_000, n_streams: int = 
         # stream's scene events
         scene_events = rate * duration_us * 1e-6 * (1.0 - spec.noise_fraction)
         spec = StreamSpec(**{**spec.__dict__, "duration_us": int(duration_us),
-                             "seed": 4000 + s, "target_scene_events": scene_events,
+                             "seed": 1000 * wl + s, "target_scene_events": scene_events,
                              knob: getattr(spec, knob) * rate / base_rate})
         st = generate(spec, threads=threads)
         st.meta.update({"target_rate": rate, "base": base})

@@ -225,6 +225,13 @@ esi_status esi_set_tile_pixels(esi_state *st, int32_t tile_pixels);
  * T do not depend on it, S and frames only to rounding. */
 esi_status esi_set_scan_run(esi_state *st, int32_t scan_run);
 
+/* An upper bound of the device scratch that one state of a W x H sensor
+ * allocates for integrate calls (esi_integrate_window or esi_integrate_batch)
+ * of at most n_events events each, growth margin included: what a caller that
+ * budgets device memory per state (a server admitting sessions) must reserve
+ * beside the state itself (esi_state_bytes).  Uses the current device. */
+esi_status esi_scratch_bound(int32_t width, int32_t height, size_t n_events, size_t *bytes);
+
 /* Sensor size of a state. */
 esi_status esi_get_size(const esi_state *st, int32_t *width, int32_t *height);
 

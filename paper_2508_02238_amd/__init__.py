@@ -88,6 +88,8 @@ _SIGNATURES = [
                                            ctypes.POINTER(_VP), _VP]),
     ("esi_set_tile_pixels", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("esi_set_scan_run", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("esi_scratch_bound", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t,
+                                         ctypes.POINTER(ctypes.c_size_t)]),
     ("esi_status_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
@@ -166,6 +168,12 @@ def esi_set_scan_run(st, scan_run: int) -> int:
     return lib.esi_set_scan_run(_VP(st), int(scan_run))
 
 
+def esi_scratch_bound(width: int, height: int, n_events: int):
+    out = ctypes.c_size_t()
+    rc = lib.esi_scratch_bound(int(width), int(height), int(n_events), ctypes.byref(out))
+    return rc, out.value
+
+
 def esi_batch_create(max_items: int):
     out = _VP()
     rc = lib.esi_batch_create(int(max_items), ctypes.byref(out))
@@ -187,6 +195,20 @@ def esi_integrate_batch(batch, states, events, t_frames=None, n_frames=None, fra
     return lib.esi_integrate_batch(_VP(batch), m, st, ev, arr(t_frames, _VP),
                                    arr(n_frames, ctypes.c_int32), arr(frames, _VP),
                                    arr(frames_u8, _VP), _VP(stream))
+
+
+def esi_integrate_batch_arrays(batch, n: int, states, events, t_frames, n_frames, frames,
+                               stream: int = 0) -> int:
+    """esi_integrate_batch with its per-item arguments as numpy arrays in
+    the C layout (no per-item Python objects): states, t_frames and frames
+    uint64 pointer arrays of n entries, events a structured array of n
+    esi_events (x, y, t, p pointers and n as uint64), n_frames int32."""
+    vp = lambda a: ctypes.cast(a.ctypes.data, ctypes.POINTER(_VP))
+    return lib.esi_integrate_batch(_VP(batch), int(n), vp(states),
+                                   ctypes.cast(events.ctypes.data, ctypes.POINTER(esi_events)),
+                                   vp(t_frames),
+                                   ctypes.cast(n_frames.ctypes.data, ctypes.POINTER(ctypes.c_int32)),
+                                   vp(frames), None, _VP(stream))
 
 
 def esi_snapshot_frame(st, t_frame_us: int, frame_ptr, u8_ptr, stream: int = 0) -> int:

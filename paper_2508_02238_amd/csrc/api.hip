@@ -694,6 +694,20 @@ esi_status esi_set_tile_pixels(esi_state* st, int32_t tile_pixels)
     return ESI_OK;
 }
 
+esi_status esi_scratch_bound(int32_t width, int32_t height, size_t n_events, size_t* bytes)
+{
+    if (!bytes || width < 1 || height < 1 || width > kMaxSide || height > kMaxSide ||
+        n_events >= ((size_t)1 << 31))
+        return ESI_ERR_INVALID_ARG;
+    // the most bucketing ranges any call gives one state: the resident
+    // bucketing workgroups of the smallest tile table
+    const int64_t npix = band_rows(width, height) * width;
+    const Schedule sc = make_schedule(npix, (int64_t)n_events, bucket_slots(1));
+    const ScratchPlan p = scratch_plan(sc, (int64_t)n_events, 0);
+    *bytes = n_events > 0 ? p.need + p.need / 4 : 0;  // with the growth margin of call_scratch
+    return ESI_OK;
+}
+
 esi_status esi_set_scan_run(esi_state* st, int32_t scan_run)
 {
     if (!st || scan_run < 0)

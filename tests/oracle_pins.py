@@ -262,40 +262,71 @@ def pin_brute_force_eq5(lib):
             assert st.T[r] == times[-1]
 
 
-def pin_brute_force_clamped(lib):
-    """Tiny sensors, short random runs with clamp hits: a direct transcription
-    of the per-event steps (pure Python, one event at a time) gives the same
-    state; this checks the placement of the clamp against Alg. 2 ordering."""
+def pin_clamp_saturation(lib):
+    """Closed forms of the per-event clamp (Eq. (13) inside Alg. 2's loop),
+    independent of any history: a burst of m same-time +1 events with
+    m C >= S_max - S_min leaves S at exactly S_max (d(0) = 1: every add is
+    followed by the clamp), a -1 burst at exactly S_min; from that saturated
+    state a run that stays inside the bounds follows the unrolled sum of
+    Eq. (5) started at S_max (add then decay: S_n = S_max prod d_j +
+    C sum p_i prod_{j >= i} d_j; decay then add: S_max prod d_j +
+    C sum p_i prod_{j > i} d_j).  Dyadic values (C = 1/4, bounds -1/2 and
+    3/4, kD in {0, 1/4, 1/2}, b = 2): exact equality.  A clamp applied at
+    the output only, or before the add, leaves S outside the bounds after
+    the burst."""
     rng = np.random.default_rng(15)
-    for (W, H) in [(1, 1), (2, 2), (4, 3)]:
-        for trial in range(6):
-            k = [0.0, 1e-6, 2e-5][trial % 3]
-            b = [0.5, 2.0, 4.7][trial % 3]
-            C = 0.3
-            lo, hi = -0.3, 0.7
-            n = 200
-            x, y, t, p = _random_stream(rng, W, H, n, 2 * 10**5)
-            flags = trial % 2
-            st = oracle.State(W, H, oracle.Params(C=C, k_per_us=k, b=b, s_min=lo,
-                                                  s_max=hi, flags=flags), lib=lib)
-            st.integrate(x, y, t, p, want_frames=False)
-            S = [0.0] * (W * H)
-            T = [0] * (W * H)
-            for i in range(n):
-                q = int(y[i]) * W + int(x[i])
-                s = C if p[i] > 0 else -C
-                dt = max(int(t[i]) - T[q], 0)
-                u = 1.0 - k * dt
-                d = u ** b if u > 0 else 0.0
-                v = S[q] * d + s if flags else (S[q] + s) * d
-                S[q] = min(max(v, lo), hi)
-                T[q] = int(t[i])
-            assert np.allclose(st.S, S, rtol=0, atol=1e-14), (W, H, trial)
+    C, lo, hi, k = 0.25, -0.5, 0.75, 1e-6
+    m = 6                                   # 6 C = 1.5 >= hi - lo = 1.25
+    gaps = [0, 250_000, 500_000]            # k D in {0, 1/4, 1/2}
+    for flags in (0, 1):
+        for sign in (1, -1):
+            W, H = 3, 2
+            xs, ys, ts, ps = [], [], [], []
+            expect = {}
+            for q in range(W * H):
+                x, y = q % W, q // W
+                t = int(rng.integers(1_000, 50_000))
+                # history: a few random events before the burst
+                for _ in range(int(rng.integers(0, 4))):
+                    t += int(rng.integers(0, 300_000))
+                    xs.append(x); ys.append(y); ts.append(t)
+                    ps.append(int(rng.choice([-1, 1])))
+                t += int(rng.integers(1, 100_000))
+                for _ in range(m):                      # the saturating burst
+                    xs.append(x); ys.append(y); ts.append(t); ps.append(sign)
+                S = hi if sign > 0 else lo
+                # a run inside the bounds: polarities back towards 0 first
+                seq = [-sign, sign, -sign, -sign, sign][:int(rng.integers(0, 6))]
+                prods, terms = [], []
+                for pol in seq:
+                    t += gaps[int(rng.integers(0, 3))]
+                    xs.append(x); ys.append(y); ts.append(t); ps.append(pol)
+                run_t = ts[len(ts) - len(seq) - 1:]        # burst time, then the run
+                d = [(1.0 - k * (run_t[j + 1] - run_t[j])) ** 2 for j in range(len(seq))]
+                # Eq. (5) from the saturated state, both orders, exact
+                tot = S
+                for j in range(len(seq)):
+                    tot *= d[j]
+                for i, pol in enumerate(seq):
+                    w = 1.0
+                    for j in range(i if flags == 0 else i + 1, len(seq)):
+                        w *= d[j]
+                    tot += C * pol * w
+                # the run must stay within the bounds (the clamp a no-op) for the form to hold
+                part = S
+                for i, pol in enumerate(seq):
+                    part = (part + C * pol) * d[i] if flags == 0 else part * d[i] + C * pol
+                    assert lo <= part <= hi
+                expect[q] = tot
+            order = np.argsort(np.array(ts), kind="stable")
+            st = oracle.State(W, H, oracle.Params(C=C, k_per_us=k, b=2.0, s_min=lo, s_max=hi,
+                                                  flags=flags), lib=lib)
+            st.integrate(np.array(xs, np.uint16)[order], np.array(ys, np.uint16)[order],
+                         np.array(ts, np.int64)[order], np.array(ps, np.int8)[order],
+                         want_frames=False)
+            for q, v in expect.items():
+                assert st.S[q] == v, (flags, sign, q, st.S[q], v)
 
-
-# --------------------------------------------------------------------------
-# Invariants
-# --------------------------------------------------------------------------
 
 def pin_linearity_symmetry(lib):
     """With no clamp hit, S is linear in C (doubling C doubles S exactly)

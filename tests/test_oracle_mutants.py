@@ -30,6 +30,10 @@ MUTANTS = [
     ("clamp_min_dropped", "    if (s < s_min)\n        s = s_min;\n", "\n"),
     ("clamp_before_update", "        S[q] = clamp_s(S[q], s_min, s_max);\n        N[q] += 1;",
      "        N[q] += 1;"),
+    # the clamp ahead of the add and decay instead of after them
+    ("clamp_before_add",
+     "            S[q] = (S[q] + pol * C) * d;\n        T[q] = t[i];\n        S[q] = clamp_s(S[q], s_min, s_max);\n",
+     "            S[q] = (clamp_s(S[q], s_min, s_max) + pol * C) * d;\n        T[q] = t[i];\n"),
     ("frame_membership_off_by_one", "while (j < nf && t_frames[j] < t[i])",
      "while (j < nf && t_frames[j] <= t[i])"),
     ("map_denominator", "return (v - s_min) / (s_max - s_min);", "return (v - s_min) / (s_max + 1.0);"),

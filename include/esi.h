@@ -221,8 +221,11 @@ esi_status esi_set_tile_pixels(esi_state *st, int32_t tile_pixels);
  * scan_run events is integrated by its own lane, one event after the other,
  * and a longer run by its whole wave, 64 events at a time, as a scan of the
  * per-event clamp-affine maps (hot pixels and same-time bursts).  scan_run
- * >= 0, 0 for the default (64); e.g. INT32_MAX turns the scan off.  N, P and
- * T do not depend on it, S and frames only to rounding. */
+ * >= 0; INT32_MAX turns the scan off; 0 for the default: 64 for tiles of
+ * 512 pixels and more, off for 256-pixel tiles (their one-pixel-per-thread
+ * kernel is slowed by the scan's code alone, so it is compiled without it
+ * unless a threshold is set).  N, P and T do not depend on it, S and frames
+ * only to rounding. */
 esi_status esi_set_scan_run(esi_state *st, int32_t scan_run);
 
 /* An upper bound of the device scratch that one state of a W x H sensor

@@ -21,6 +21,16 @@ using namespace esi;
 // exceeds one lane's loop.
 constexpr int kDefaultScanRun = 64;
 
+// The scan threshold a call uses: the state's (set by esi_set_scan_run), or
+// by default 64 for tiles of two or more pixels per thread and off for one
+// pixel per thread, whose kernel the scan's code alone slows.
+int effective_scan_run(int state_scan_run, int ppt)
+{
+    if (state_scan_run > 0)
+        return state_scan_run;
+    return ppt == 1 ? kScanOff : kDefaultScanRun;
+}
+
 struct esi_state {
     int32_t W = 0, H = 0;
     int64_t npix = 0;
@@ -39,7 +49,7 @@ struct esi_state {
     int bucket_slots = 1024;  // bucketing workgroups resident at once
     int integ_slots[4] = {1 << 30, 1 << 30, 1 << 30, 1 << 30};  // per ppt 1, 2, 4, 8
     int min_ppt = 1;          // smallest pixels per thread of the integration tiles
-    int scan_run = kDefaultScanRun;  // longer runs per chunk take the wave's scan
+    int scan_run = 0;  // longer runs per chunk take the wave's scan (0: by tile size)
     bool state_in_range = true;  // every S in [s_min, s_max] (false after importing one outside)
     bool poisoned = false;
     uint64_t calls = 0;
@@ -125,10 +135,10 @@ bool params_ok(const esi_params* p)
            (p->flags & ~(uint32_t)(ESI_DECAY_THEN_ADD | ESI_SNAPSHOT_LAZY | ESI_DECAY_EXP)) == 0;
 }
 
-MethodParams method_params(const esi_params& p, int scan_run)
+MethodParams method_params(const esi_params& p)
 {
     MethodParams mp{};
-    mp.scan_run = scan_run;
+    mp.scan_run = kDefaultScanRun;
     mp.C = p.C;
     mp.k = p.k_per_us;
     mp.b = p.b;
@@ -471,7 +481,7 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
         return ESI_ERR_POISONED;
     DeviceGuard g(st->device);
     const int64_t n = (int64_t)ev->n;
-    MethodParams mp = method_params(st->params, st->scan_run);
+    MethodParams mp = method_params(st->params);
     if (!st->state_in_range)
         mp.need_clamp = 1;
     // the sensor in bands of rows, one pass of the kernels each (one band
@@ -527,6 +537,7 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
         if (pe && y0 == 0 && hipEventRecord(pe[1], stream) != hipSuccess)
             return hip_fail(st);
         if (n > 0 || n_frames > 0) {
+            mp.scan_run = effective_scan_run(st->scan_run, sc.ppt);
             if (launch_integrate(evd, sd, sc, cs, mp, fo, st->diag, stream) != hipSuccess)
                 return hip_fail(st);
         }
@@ -563,7 +574,7 @@ esi_status esi_snapshot_frame(esi_state* st, int64_t t_frame_us, float* frame, u
     if (st->poisoned)
         return ESI_ERR_POISONED;
     DeviceGuard g(st->device);
-    if (launch_snapshot(st->dev, method_params(st->params, st->scan_run), t_frame_us, frame, u8, stream) !=
+    if (launch_snapshot(st->dev, method_params(st->params), t_frame_us, frame, u8, stream) !=
         hipSuccess)
         return hip_fail(st);
     return ESI_OK;
@@ -712,7 +723,7 @@ esi_status esi_set_scan_run(esi_state* st, int32_t scan_run)
 {
     if (!st || scan_run < 0)
         return ESI_ERR_INVALID_ARG;
-    st->scan_run = scan_run ? scan_run : kDefaultScanRun;
+    st->scan_run = scan_run;
     return ESI_OK;
 }
 
@@ -868,7 +879,8 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         x = BatchItem{};
         x.ev = EventsDev{events[i].x, events[i].y, events[i].t, events[i].p, n, 0, st->H};
         x.st = st->dev;
-        x.mp = method_params(st->params, st->scan_run);
+        x.mp = method_params(st->params);
+        x.mp.scan_run = effective_scan_run(st->scan_run, sc[i].ppt);
         if (!st->state_in_range)
             x.mp.need_clamp = 1;
         const int32_t nf = n_frames ? n_frames[i] : 0;
@@ -888,7 +900,8 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
             x.nseg = (int)scan_segments(x.B);
             x.cols = (x.K + 255) / 256;
         }
-        cls[i] = sc[i].ppt * 8 + decay_kind(x.mp);
+        // integration class: tile size, decay kind, scan compiled in or not
+        cls[i] = (sc[i].ppt * 2 + (x.mp.scan_run != kScanOff ? 1 : 0)) * 8 + decay_kind(x.mp);
     }
     // items ordered by class, so that each integration launch covers a range
     std::vector<int> order(n_items);
@@ -973,7 +986,8 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         while (k1 < n_items && cls[order[k1]] == cls[order[k0]])
             ++k1;
         const int c = cls[order[k0]];
-        if (launch_integrate_batch(bd, k0, k1, tb[k0], tb[k1] - tb[k0], c / 8, c % 8, stream) !=
+        if (launch_integrate_batch(bd, k0, k1, tb[k0], tb[k1] - tb[k0], c / 16, c % 8,
+                                   (c / 8) % 2 == 1, stream) !=
             hipSuccess)
             return fail();
         k0 = k1;

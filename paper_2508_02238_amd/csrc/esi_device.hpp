@@ -29,8 +29,11 @@ struct MethodParams {
     int need_clamp;  // a decayed state can leave [s_min, s_max]
     // a pixel's run of more than scan_run events in one chunk goes through
     // the wave's scan of its per-event maps instead of one lane's loop
+    // (kScanOff: never)
     int scan_run;
 };
+
+constexpr int kScanOff = 0x7FFFFFFF;
 
 // How the decay is evaluated: Eq. (4), d = max(1 - k dt, 0)^b, with b = 1 and
 // b = 2 exactly by multiplication and any other b by pow(); or the

@@ -289,13 +289,34 @@ __device__ __forceinline__ ChunkCtl chunk_ctl(const uint64_t* records, uint32_t 
 template <int PPT, int NB>
 constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : PPT == 2 ? 4 : 1; }
 
-template <int PPT, int NB, int BK>
+// A tile's record window [rs, re) in its bucket and the call's time origin
+// (scalar loads; a batched workgroup loads the next tile's while it works on
+// the current one).
+struct TileBounds {
+    uint32_t rs, re;
+    int64_t t_ref;
+};
+
+__device__ __forceinline__ TileBounds tile_bounds(const uint32_t* table, const uint32_t* total,
+                                                  const int64_t* ev_t, int K, int tile)
+{
+    TileBounds tb{0, 0, 0};
+    if (table) {
+        tb.rs = load_const(table, tile);
+        tb.re = (tile + 1 < K) ? load_const(table, tile + 1) : load_const(total, 0);
+        tb.t_ref = load_const(ev_t, 0);
+    }
+    return tb;
+}
+
+// SCAN: phase A's wave scan of long runs compiled in (section 3b)
+template <int PPT, int NB, int BK, bool SCAN>
 __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ records,
                                                const uint32_t* __restrict__ table,
                                                const uint32_t* __restrict__ total,
                                                const int64_t* __restrict__ ev_t, int K,
                                                StateDev st, MethodParams mp, FrameOut fo,
-                                               DiagDev* diag, int tile)
+                                               DiagDev* diag, int tile, const TileBounds& tb)
 {
     using Cfg = TileCfg<PPT, NB>;
     constexpr int TILE = Cfg::TILE;
@@ -347,14 +368,9 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
         px.P[i] = 0;
     }
 
-    // the tile's records [rs, re); read-only here, so scalar loads
-    uint32_t rs = 0, re = 0;
-    int64_t t_ref = 0;
-    if (table) {
-        rs = load_const(table, tile);
-        re = (tile + 1 < K) ? load_const(table, tile + 1) : load_const(total, 0);
-        t_ref = load_const(ev_t, 0);
-    }
+    // the tile's records [rs, re)
+    const uint32_t rs = tb.rs, re = tb.re;
+    const int64_t t_ref = tb.t_ref;
 
     int j = 0;  // first frame of the segment (uniform)
     uint32_t cs = rs;
@@ -579,23 +595,20 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
             // clamp bounds in canonical form once, not on every event
             const double s_min = __builtin_canonicalize(mp.s_min);
             const double s_max = __builtin_canonicalize(mp.s_max);
-            // runs longer than mp.scan_run are left to the wave's scan (3b)
-            uint32_t begs[PPT], ends[PPT];
-            double A0s[PPT];
-            bool lng[PPT];
+            // runs longer than mp.scan_run are left to the wave's scan (3b):
+            // only their lane masks (scalar registers) live across the loop
+            uint64_t lmask[PPT];
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 const int l = tid + i * NB;
                 const uint32_t end = min((l + 1 < TILE) ? (uint32_t)cnt[0][l + 1] : cn, cn);
                 const uint32_t beg = min((uint32_t)cnt[0][l], end);
-                begs[i] = beg;
-                ends[i] = end;
-                A0s[i] = __fma_rn(mp.k, (double)(px.T[i] - c.t_first), 1.0);
-                lng[i] = end - beg > (uint32_t)mp.scan_run;
-                if (lng[i])
+                const bool lng = SCAN && end - beg > (uint32_t)mp.scan_run;
+                lmask[i] = __ballot(lng);
+                if (lng)
                     continue;
                 double S = px.S[i];
-                double A = A0s[i];
+                double A = __fma_rn(mp.k, (double)(px.T[i] - c.t_first), 1.0);
                 uint32_t w = beg, nneg = 0;
                 int jc_prev = nfw;  // frame of the events applied so far (nfw: none)
                 auto run = [&](auto decay_then_add) {
@@ -653,85 +666,84 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
             }
 
             // 3b. each run longer than mp.scan_run, one after the other, by
-            // the whole wave of its pixel: blocks of 64 events, lane e taking
-            // event b0 + e.  Every lane builds its event's map (the decay
-            // from the previous event's time, lane e - 1's kt, or the pixel's
-            // A for the run's first event), the wave scans the maps
-            // (wave_scan), and lane e applies the composed map to the state
-            // before the block, which gives the state after its event.  The
-            // change-list entries are the events whose next event belongs to
-            // a later frame (or that end the run), at positions counted with
-            // a ballot; they land at or before their own event, behind every
-            // read of the block, and the next block only reads later events.
-            auto scan_run = [&](auto decay_then_add, int i, int owner) {
-                const uint32_t beg = (uint32_t)__builtin_amdgcn_readlane((int)begs[i], owner);
-                const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int)ends[i], owner);
-                const uint32_t l = (uint32_t)(tid - lane + owner + i * NB);
-                double S = readlane_f64(px.S[i], owner);
-                double A = readlane_f64(A0s[i], owner);
-                // the run's last event, read before any entry can overwrite it
-                const int64_t t_last = t_ref + record_dt(sorted[end - 1]);
-                uint32_t w = beg, nneg = 0;
-                for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
-                    const uint32_t e = b0 + (uint32_t)lane;
-                    const bool valid = e < end;
-                    const bool has_next = e + 1u < end;
-                    const double kt = ktvs[valid ? e : b0];
-                    const double kt_n = ktvs[has_next ? e + 1u : b0];
-                    const uint32_t low = (uint32_t)__double_as_longlong(kt);
-                    const int jc = (int)(low & 0x7Fu);
-                    const uint32_t neg = (low >> 7) & 1u;
-                    const int jc_n = has_next ? (int)((uint32_t)__double_as_longlong(kt_n) & 0x7Fu) : -1;
-                    // the previous event's kt (wave_shr:1); lane 0 takes A
-                    const double kt_p = dpp_f64<0x138>(0.0, kt);
-                    const double A_p = (lane == 0) ? A : 1.0 + kt_p;
-                    const double d = decay_from_base<BK>(A_p - kt, mp.b);
-                    const double sc = __hiloint2double((int)(c_hi + (neg << 31)), (int)c_lo);
-                    ClampAffine f = clamp_affine_identity();
-                    if (valid) {
-                        f.a = d;
-                        f.b = decltype(decay_then_add)::value ? sc : d * sc;
-                        f.lo = s_min;
-                        f.hi = s_max;
-                    }
-                    f = wave_scan(f);
-                    const double S_e = apply(f, S);
-                    const bool ge = valid && jc < nfw && jc_n != jc;
-                    const uint64_t gm = __ballot(ge);
-                    if (ge) {
-                        const uint32_t at = w + (uint32_t)__popcll(gm & ((1ull << lane) - 1ull));
-                        const double A_e = 1.0 + kt;
-                        chg_S[at] = S_e * mp.inv_range;
-                        chg_A[at] = (BK == kDecayExp) ? exp(A_e + dA - 1.0) : A_e + dA;
-                        chg_j[at + l] = (uint16_t)jc;
-                    }
-                    const int last = (int)min(end - b0, (uint32_t)kWave) - 1;
-                    S = readlane_f64(S_e, last);
-                    A = 1.0 + readlane_f64(kt, last);
-                    w += (uint32_t)__popcll(gm);
-                    nneg += (uint32_t)__popcll(__ballot(valid && neg != 0u));
-                }
-                if (lane == owner) {
-                    px.S[i] = S;
-                    px.T[i] = t_last;
-                    px.N[i] += end - beg;
-                    px.P[i] += (int32_t)(end - beg) - 2 * (int32_t)nneg;
-                    chg_j[w + l] = 0xFFFF;
-                    px.jn[i] = chg_j[beg + l];
-                    px.eo[i] = 8u * beg;
-                    px.jo[i] = 2u * (beg + l + 1u);
-                }
-            };
+            // the whole wave of its pixel, 64 events at a time: lane e takes
+            // event b0 + e and builds its map (the decay from the previous
+            // event's time, lane e - 1's kt, or the pixel's A for the run's
+            // first event), the wave scans the maps (wave_scan), and lane e
+            // applies the composed map to the state before the block, which
+            // gives the state after its event.  The change-list entries are
+            // the events whose next event belongs to a later frame (or that
+            // end the run), at positions counted with a ballot; they land at
+            // or before their own event, behind every read of the block, and
+            // the next block only reads later events.
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                uint64_t todo = __ballot(lng[i]);
+            for (int i = 0; i < (SCAN ? PPT : 0); ++i) {
+                uint64_t todo = lmask[i];
                 while (todo) {
                     const int owner = (int)__builtin_ctzll(todo);
                     todo &= todo - 1ull;
-                    if (mp.decay_then_add)
-                        scan_run(std::true_type{}, i, owner);
-                    else
-                        scan_run(std::false_type{}, i, owner);
+                    const uint32_t l = (uint32_t)(tid - lane + owner + i * NB);
+                    const uint32_t end = min((l + 1 < TILE) ? (uint32_t)cnt[0][l + 1] : cn, cn);
+                    const uint32_t beg = min((uint32_t)cnt[0][l], end);
+                    double S = readlane_f64(px.S[i], owner);
+                    const int64_t T0 =
+                        (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                                       (int)((uint64_t)px.T[i] >> 32), owner) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)px.T[i], owner));
+                    double A = __fma_rn(mp.k, (double)(T0 - c.t_first), 1.0);
+                    // the run's last event, read before any entry can overwrite it
+                    const int64_t t_last = t_ref + record_dt(sorted[end - 1]);
+                    uint32_t w = beg, nneg = 0;
+                    for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
+                        const uint32_t e = b0 + (uint32_t)lane;
+                        const bool valid = e < end;
+                        const bool has_next = e + 1u < end;
+                        const double kt = ktvs[valid ? e : b0];
+                        const double kt_n = ktvs[has_next ? e + 1u : b0];
+                        const uint32_t low = (uint32_t)__double_as_longlong(kt);
+                        const int jc = (int)(low & 0x7Fu);
+                        const uint32_t neg = (low >> 7) & 1u;
+                        const int jc_n =
+                            has_next ? (int)((uint32_t)__double_as_longlong(kt_n) & 0x7Fu) : -1;
+                        // the previous event's kt (wave_shr:1); lane 0 takes A
+                        const double kt_p = dpp_f64<0x138>(0.0, kt);
+                        const double A_p = (lane == 0) ? A : 1.0 + kt_p;
+                        const double d = decay_from_base<BK>(A_p - kt, mp.b);
+                        const double sc = __hiloint2double((int)(c_hi + (neg << 31)), (int)c_lo);
+                        ClampAffine f = clamp_affine_identity();
+                        if (valid) {
+                            f.a = d;
+                            f.b = mp.decay_then_add ? sc : d * sc;
+                            f.lo = s_min;
+                            f.hi = s_max;
+                        }
+                        f = wave_scan(f);
+                        const double S_e = apply(f, S);
+                        const bool ge = valid && jc < nfw && jc_n != jc;
+                        const uint64_t gm = __ballot(ge);
+                        if (ge) {
+                            const uint32_t at = w + (uint32_t)__popcll(gm & ((1ull << lane) - 1ull));
+                            const double A_e = 1.0 + kt;
+                            chg_S[at] = S_e * mp.inv_range;
+                            chg_A[at] = (BK == kDecayExp) ? exp(A_e + dA - 1.0) : A_e + dA;
+                            chg_j[at + l] = (uint16_t)jc;
+                        }
+                        const int last = (int)min(end - b0, (uint32_t)kWave) - 1;
+                        S = readlane_f64(S_e, last);
+                        A = 1.0 + readlane_f64(kt, last);
+                        w += (uint32_t)__popcll(gm);
+                        nneg += (uint32_t)__popcll(__ballot(valid && neg != 0u));
+                    }
+                    if (lane == owner) {
+                        px.S[i] = S;
+                        px.T[i] = t_last;
+                        px.N[i] += end - beg;
+                        px.P[i] += (int32_t)(end - beg) - 2 * (int32_t)nneg;
+                        chg_j[w + l] = 0xFFFF;
+                        px.jn[i] = chg_j[beg + l];
+                        px.eo[i] = 8u * beg;
+                        px.jo[i] = 2u * (beg + l + 1u);
+                    }
                 }
             }
         } else {
@@ -791,7 +803,7 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
 // One workgroup per tile of one call.  Workgroups start in index order, so
 // with `order` (the tiles by event count, largest first) the longest tiles
 // start first and the short ones fill the end of the launch.
-template <int PPT, int NB, int BK>
+template <int PPT, int NB, int BK, bool SCAN>
 __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrate(
     const uint64_t* __restrict__ records, const uint32_t* __restrict__ table,
     const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t,
@@ -799,14 +811,15 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
     DiagDev* diag)
 {
     const int tile = order ? (int)load_const(order, blockIdx.x) : (int)blockIdx.x;
-    integrate_body<PPT, NB, BK>(records, table, total, ev_t, K, st, mp, fo, diag, tile);
+    integrate_body<PPT, NB, BK, SCAN>(records, table, total, ev_t, K, st, mp, fo, diag, tile,
+                                      tile_bounds(table, total, ev_t, K, tile));
 }
 
 // Batched: the tiles of items [i0, i1) (one tile size and decay kind), work
 // indices [tile0, tile0 + tiles) laid out item by item; each workgroup takes
 // a contiguous share of them, so it looks its item up once and then only
 // steps to the next item.
-template <int PPT, int NB, int BK>
+template <int PPT, int NB, int BK, bool SCAN>
 __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void kb_integrate(
     BatchDev b, int i0, int i1, uint32_t tile0, uint32_t tiles)
 {
@@ -833,8 +846,10 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void kb_integra
             next = load_const(b.tile_base, i + 1);
         }
         const BatchItem& it = b.items[i];
-        integrate_body<PPT, NB, BK>(it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K, it.st,
-                                    it.mp, it.fo, it.diag, (int)(w - first));
+        const int tile = (int)(w - first);
+        integrate_body<PPT, NB, BK, SCAN>(it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K,
+                                          it.st, it.mp, it.fo, it.diag, tile,
+                                          tile_bounds(it.cs.table, it.cs.total, it.ev.t, it.K, tile));
         __syncthreads();  // LDS is reused by the next tile
     }
 }
@@ -878,11 +893,19 @@ hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Sch
                               DiagDev* diag, hipStream_t stream)
 {
     const bool has = ev.n > 0;
-    hipLaunchKernelGGL((k_integrate<PPT, NB, BK>), dim3(sc.ntiles), dim3(NB), 0, stream,
-                       has ? cs.records : nullptr, has ? cs.table : nullptr,
-                       has ? cs.total : nullptr, has ? ev.t : nullptr,
-                       (has && sc.ordered) ? cs.order : nullptr,
-                       sc.ntiles, st, mp, fo, diag);
+    // tiles of one pixel per thread leave the scan out when it is off: its
+    // code alone slows that kernel (section 3b)
+    auto go = [&](auto scan) {
+        hipLaunchKernelGGL((k_integrate<PPT, NB, BK, decltype(scan)::value>), dim3(sc.ntiles),
+                           dim3(NB), 0, stream, has ? cs.records : nullptr,
+                           has ? cs.table : nullptr, has ? cs.total : nullptr,
+                           has ? ev.t : nullptr, (has && sc.ordered) ? cs.order : nullptr,
+                           sc.ntiles, st, mp, fo, diag);
+    };
+    if (PPT == 1 && mp.scan_run == kScanOff)
+        go(std::false_type{});
+    else
+        go(std::true_type{});
     return hipGetLastError();
 }
 
@@ -914,16 +937,16 @@ int integrate_slots(int ppt)
     if (e == hipSuccess) {
         switch (ppt) {
         case 1:
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<1, 256, kDecayB2>, 256, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<1, 256, kDecayB2, true>, 256, 0);
             break;
         case 2:
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<2, 256, kDecayB2>, 256, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<2, 256, kDecayB2, true>, 256, 0);
             break;
         case 4:
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<4, 256, kDecayB2>, 256, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<4, 256, kDecayB2, true>, 256, 0);
             break;
         default:
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<8, 256, kDecayB2>, 256, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<8, 256, kDecayB2, true>, 256, 0);
         }
     }
     if (e != hipSuccess) {
@@ -961,55 +984,66 @@ hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Sched
 
 namespace {
 
-template <int PPT, int BK>
-hipError_t launch_integrate_batch_t(const BatchDev& b, int i0, int i1, uint32_t tile0,
+template <int PPT, int BK, bool SCAN>
+hipError_t launch_integrate_batch_s(const BatchDev& b, int i0, int i1, uint32_t tile0,
                                     uint32_t tiles, hipStream_t stream)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb_integrate<PPT, 256, BK>, 256, 0) !=
-            hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb_integrate<PPT, 256, BK, SCAN>,
+                                                     256, 0) != hipSuccess)
         return hipGetLastError();
     // a few workgroups per slot: contiguous shares, balanced by the dispatcher
     const uint32_t grid = std::min<uint32_t>(tiles, 4u * (uint32_t)std::max(1, cus * per_cu));
-    hipLaunchKernelGGL((kb_integrate<PPT, 256, BK>), dim3(grid), dim3(256), 0, stream, b, i0, i1,
-                       tile0, tiles);
+    hipLaunchKernelGGL((kb_integrate<PPT, 256, BK, SCAN>), dim3(grid), dim3(256), 0, stream, b,
+                       i0, i1, tile0, tiles);
     return hipGetLastError();
+}
+
+// scan: the items of the launch have the scan on (their class; tiles of
+// one pixel per thread only leave it out)
+template <int PPT, int BK>
+hipError_t launch_integrate_batch_t(const BatchDev& b, int i0, int i1, uint32_t tile0,
+                                    uint32_t tiles, bool scan, hipStream_t stream)
+{
+    if (PPT == 1 && !scan)
+        return launch_integrate_batch_s<PPT, BK, false>(b, i0, i1, tile0, tiles, stream);
+    return launch_integrate_batch_s<PPT, BK, true>(b, i0, i1, tile0, tiles, stream);
 }
 
 template <int PPT>
 hipError_t launch_integrate_batch_p(const BatchDev& b, int i0, int i1, uint32_t tile0,
-                                    uint32_t tiles, int bk, hipStream_t stream)
+                                    uint32_t tiles, int bk, bool scan, hipStream_t stream)
 {
     switch (bk) {
     case kDecayB1:
-        return launch_integrate_batch_t<PPT, kDecayB1>(b, i0, i1, tile0, tiles, stream);
+        return launch_integrate_batch_t<PPT, kDecayB1>(b, i0, i1, tile0, tiles, scan, stream);
     case kDecayB2:
-        return launch_integrate_batch_t<PPT, kDecayB2>(b, i0, i1, tile0, tiles, stream);
+        return launch_integrate_batch_t<PPT, kDecayB2>(b, i0, i1, tile0, tiles, scan, stream);
     case kDecayExp:
-        return launch_integrate_batch_t<PPT, kDecayExp>(b, i0, i1, tile0, tiles, stream);
+        return launch_integrate_batch_t<PPT, kDecayExp>(b, i0, i1, tile0, tiles, scan, stream);
     default:
-        return launch_integrate_batch_t<PPT, kDecayPow>(b, i0, i1, tile0, tiles, stream);
+        return launch_integrate_batch_t<PPT, kDecayPow>(b, i0, i1, tile0, tiles, scan, stream);
     }
 }
 
 }  // namespace
 
 hipError_t launch_integrate_batch(const BatchDev& b, int i0, int i1, uint32_t tile0,
-                                  uint32_t tiles, int ppt, int bk, hipStream_t stream)
+                                  uint32_t tiles, int ppt, int bk, bool scan, hipStream_t stream)
 {
     if (tiles == 0)
         return hipSuccess;
     switch (ppt) {
     case 1:
-        return launch_integrate_batch_p<1>(b, i0, i1, tile0, tiles, bk, stream);
+        return launch_integrate_batch_p<1>(b, i0, i1, tile0, tiles, bk, scan, stream);
     case 2:
-        return launch_integrate_batch_p<2>(b, i0, i1, tile0, tiles, bk, stream);
+        return launch_integrate_batch_p<2>(b, i0, i1, tile0, tiles, bk, scan, stream);
     case 4:
-        return launch_integrate_batch_p<4>(b, i0, i1, tile0, tiles, bk, stream);
+        return launch_integrate_batch_p<4>(b, i0, i1, tile0, tiles, bk, scan, stream);
     case 8:
-        return launch_integrate_batch_p<8>(b, i0, i1, tile0, tiles, bk, stream);
+        return launch_integrate_batch_p<8>(b, i0, i1, tile0, tiles, bk, scan, stream);
     default:
         return hipErrorInvalidValue;
     }

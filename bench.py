@@ -46,21 +46,16 @@ def algorithmic_bytes(n: int, npix: int, nf: int, u8: bool, f32: bool = True) ->
 
 def measured_traffic(workload: str, fps: float):
     """HBM bytes per call of the call's kernels (bucketing and integration)
-    from the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
-    each scaled by the reading of a plain copy of known size), or None when
-    no summary exists for this workload or the kernel sources changed since
-    it was taken.  Returns (total, {kernel group: bytes})."""
-    import hashlib
+    from the committed counter summary (FETCH_SIZE and WRITE_SIZE, each
+    scaled by the reading of a plain copy of known size), or None when no
+    summary exists for this workload or the kernel sources changed since it
+    was taken.  Returns (total, {kernel group: bytes})."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{fps:g}fps.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    for src in rec["sources"]:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+    if _sources_hash(rec["sources"]) != rec["sources_sha256_16"]:
         return None
     groups = {g: int(v["read_bytes"]) + int(v["write_bytes"]) for g, v in rec["groups"].items()}
     return sum(groups.values()), groups
@@ -104,6 +99,88 @@ def cpu_baseline(s, tf, prm, sample_s: float, min_s: float, threads: int):
             "cpu_model": _cpu_model()}
 
 
+TRAFFIC_SOURCES = ["paper_2508_02238_amd/csrc/bucket.hip", "paper_2508_02238_amd/csrc/integrate.hip",
+                   "paper_2508_02238_amd/csrc/esi_device.hpp",
+                   "paper_2508_02238_amd/csrc/esi_internal.hpp"]
+
+
+def _sources_hash(sources) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _short_kernel_name(name: str) -> str:
+    """k_bucket<4096> from 'void esi::(anonymous namespace)::k_bucket<4096>(...)'."""
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0].replace("esi::", "")
+
+
+def _counter_means(path: str) -> dict:
+    """Mean counter value (KiB) per kernel name over its dispatches, from a
+    rocprofv3 counter_collection CSV; the copy probe's dispatches kept apart."""
+    import csv
+    import collections
+    vals = collections.defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return vals
+
+
+def write_traffic(workload: str, fps: float, fetch_csv: str, write_csv: str, probe_mb: int):
+    """The bucketing and integration kernels' HBM bytes per call from two
+    rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
+    scaled by what the counter reads for the plain copy of probe_mb MiB the
+    run ended with: written to profiles/traffic_<workload>_<fps>fps.json
+    with the hash of the kernel sources (bench.py reports null once they
+    change); returns the per-kernel table."""
+    fetch, write = _counter_means(fetch_csv), _counter_means(write_csv)
+    copy = "__amd_rocclr_copyBuffer"
+    probe_kib = probe_mb * 1024.0
+    f_scale = probe_kib / max(fetch[copy])
+    w_scale = probe_kib / max(write[copy])
+    groups = {"bucketing": ("k_hist", "k_seg_sum", "k_seg_down", "k_order", "k_bucket"),
+              "integration": ("k_integrate",)}
+    out = {"workload": workload, "fps": fps, "fetch_scale": round(f_scale, 4),
+           "write_scale": round(w_scale, 4), "groups": {}, "kernels": {},
+           "sources": TRAFFIC_SOURCES, "sources_sha256_16": _sources_hash(TRAFFIC_SOURCES)}
+    for name in fetch:
+        short = _short_kernel_name(name)
+        if not short.startswith(("k_", "kb_")):
+            continue   # the copy probe and torch's own kernels
+        rb = sum(fetch[name]) / len(fetch[name]) * 1024 * f_scale
+        wb = sum(write.get(name, [0.0])) / max(1, len(write.get(name, []))) * 1024 * w_scale
+        out["kernels"][short] = {"read_bytes": int(rb), "write_bytes": int(wb),
+                                 "dispatches": len(fetch[name])}
+        for g, members in groups.items():
+            if any(short.startswith(m) for m in members):
+                acc = out["groups"].setdefault(g, {"read_bytes": 0, "write_bytes": 0})
+                acc["read_bytes"] += int(rb)
+                acc["write_bytes"] += int(wb)
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{fps:g}fps.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def kernel_stats_table(stats_csv: str) -> str:
+    """Markdown table of a rocprofv3 --stats kernel summary."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = _short_kernel_name(r["Name"])
+        lines.append(f"| {name} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.1f}% |")
+    return "\n".join(lines)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,7 +220,21 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (a "
                          "known-size reference for hardware byte counters)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_<workload>_<fps>fps.json from two rocprofv3 "
+                         "counter runs (FETCH_SIZE, WRITE_SIZE) that ended with "
+                         "--copy-probe-mb 256, and exit")
+    ap.add_argument("--kernel-stats", metavar="STATS_CSV",
+                    help="print a rocprofv3 kernel_stats CSV as a markdown table, and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        out = write_traffic(args.workload, args.fps, args.write_traffic[0],
+                            args.write_traffic[1], 256)
+        print(json.dumps(out, indent=1))
+        return 0
+    if args.kernel_stats:
+        print(kernel_stats_table(args.kernel_stats))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -223,6 +223,14 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Lane l's 64-bit integer, read by the whole wave (l uniform).
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xFFFFFFFF), l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
 // Stable multisplit rank inside one wave step.  Lane l holds an element with
 // key `key` < 2^KEY_BITS (valid when `ok`); lanes are in array order.
 // Returns, for valid lanes, counter[key] (before this step) plus the number of

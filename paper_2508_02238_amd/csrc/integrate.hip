@@ -11,8 +11,9 @@
 // chunk precedes or belongs to and that no later record can reach.
 //   1. each wave holds its quarter of the chunk's records in registers
 //      (prefetched while the previous chunk was processed);
-//   2. each record finds the first frame of the segment that includes it (a
-//      fixed-step search over the segment's frame times in LDS), then a
+//   2. each record finds the first frame of the segment that includes it
+//      (ballots over the segment's frame times bound each wave step's
+//      records, then a binary search inside those bounds), then a
 //      stable counting sort by pixel inside the tile (per-wave stable ranks,
 //      an exclusive scan over (pixel, wave) counters, a scatter into LDS) makes
 //      each pixel's events of the chunk contiguous and in array order;
@@ -492,23 +493,46 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
 
         if (cn > 0) {
             // 2b. the segment frame of each record (the number of segment
-            // frames earlier than it; binary lifting with as many steps as
-            // the segment's frame count needs), kept with its rank
+            // frames earlier than it), kept with its rank.  A wave step's 64
+            // records are consecutive in the tile's array order, so (events
+            // and frames sorted) their frames lie between those of the
+            // step's first and last record.  Those two counts come from
+            // ballots over the segment's frame times, one per lane (frames
+            // lane and 64 + lane); each record then searches its step's
+            // range by binary lifting, the steps side by side with as many
+            // halvings as the widest range needs (none when no frame time
+            // falls inside any step).  Unsorted input still gives a count in
+            // [0, nfw].
             {
-                int jc[STEPS];
+                const int64_t f0 = tfl[lane];
+                const int64_t f1 = tfl[min(kWave + lane, kFrameGroup - 1)];
+                const bool v0 = lane < nfw, v1 = kWave + lane < nfw;
+                auto frames_below = [&](int64_t t) -> int {  // t uniform
+                    int c = __popcll(__ballot(v0 && f0 < t));
+                    if (nfw > kWave)
+                        c += __popcll(__ballot(v1 && f1 < t));
+                    return c;
+                };
+                int jc[STEPS], hi[STEPS];  // hi uniform
                 int64_t tr[STEPS];
+                int span = 0;
 #pragma unroll
                 for (int s = 0; s < STEPS; ++s) {
-                    jc[s] = 0;
                     tr[s] = t_ref + record_dt(rr[s]);
+                    const int ca = frames_below(readlane_i64(tr[s], 0));
+                    const int cz = frames_below(readlane_i64(tr[s], kWave - 1));
+                    jc[s] = min(ca, cz);
+                    hi[s] = max(ca, cz);
+                    span = max(span, hi[s] - jc[s]);
                 }
-                const int top = nfw > 0 ? 1 << (31 - __clz(nfw)) : 0;
-                for (int step = top; step >= 1; step >>= 1) {
+                if (span > 0) {
+                    for (int step = 1 << (31 - __clz(span)); step >= 1; step >>= 1) {
 #pragma unroll
-                    for (int s = 0; s < STEPS; ++s) {
-                        const int probe = jc[s] + step;
-                        const int64_t v = tfl[min(probe, nfw) - 1];
-                        jc[s] = (probe <= nfw && v < tr[s]) ? probe : jc[s];
+                        for (int s = 0; s < STEPS; ++s) {
+                            const int probe = jc[s] + step;
+                            const int64_t v = tfl[max(min(probe, hi[s]) - 1, 0)];
+                            jc[s] = (probe <= hi[s] && v < tr[s]) ? probe : jc[s];
+                        }
                     }
                 }
 #pragma unroll

@@ -335,7 +335,7 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
     __shared__ double ktvs[CHUNK + 1];      // k (t - t_first) of the sorted records; then
     double* chg_S = ktvs;                 // change lists: S / (s_max - s_min) after the change
     __shared__ uint16_t chg_j[CHUNK + TILE];  // change lists: frame index in the segment
-    __shared__ uint16_t cnt[WAVES][TILE];
+    __shared__ __align__(8) uint16_t cnt[WAVES][TILE];
     // representative lane per (wave, pixel) and lane masks per wave for the
     // LDS stable rank (one and two pixels per thread; larger tiles, whose
     // threads hold more registers, use the ballot rank)
@@ -456,12 +456,17 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
         }
         uint32_t rank[STEPS];
         if (cn > 0) {
-            // 2a. stable ranks inside the wave
-            for (int k = lane; k < TILE; k += kWave)
-                cnt[wave][k] = 0;
+            // 2a. stable ranks inside the wave (the ballot rank of the larger
+            // tiles skips a wave step with no record of the chunk: sparse
+            // chunks fill only their first steps)
+            for (int k = lane; k < TILE / 4; k += kWave)  // four counters per store
+                reinterpret_cast<uint64_t*>(cnt[wave])[k] = 0;
             wave_sync();
 #pragma unroll
             for (int s = 0; s < STEPS; ++s) {
+                rank[s] = 0;
+                if (!kOrRank && (uint32_t)(wave * PER_WAVE + s * kWave) >= cn)  // uniform
+                    continue;
                 const uint32_t c_ = (uint32_t)(wave * PER_WAVE + s * kWave + lane);
                 const uint32_t key = record_lpx(rr[s]) & (TILE - 1);
                 if (kOrRank)

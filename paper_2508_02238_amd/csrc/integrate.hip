@@ -310,6 +310,49 @@ __device__ __forceinline__ TileBounds tile_bounds(const uint32_t* table, const u
     return tb;
 }
 
+// PPT consecutive 16-bit counters as one LDS word (2, 4, 8 or 16 bytes).
+template <int PPT>
+struct CounterWord;
+template <>
+struct CounterWord<1> {
+    using T = uint16_t;
+    __device__ static uint32_t get(T v, int) { return v; }
+    __device__ static void set(T& v, int, uint32_t x) { v = (uint16_t)x; }
+};
+template <>
+struct CounterWord<2> {
+    using T = uint32_t;
+    __device__ static uint32_t get(T v, int i) { return (v >> (16 * i)) & 0xFFFFu; }
+    __device__ static void set(T& v, int i, uint32_t x) { v |= (x & 0xFFFFu) << (16 * i); }
+};
+template <>
+struct CounterWord<4> {
+    using T = uint64_t;
+    __device__ static uint32_t get(T v, int i) { return (uint32_t)(v >> (16 * i)) & 0xFFFFu; }
+    __device__ static void set(T& v, int i, uint32_t x) { v |= (uint64_t)(x & 0xFFFFu) << (16 * i); }
+};
+template <>
+struct CounterWord<8> {
+    using T = uint4;
+    __device__ static uint32_t get(const T& v, int i)
+    {
+        const uint32_t w = i < 2 ? v.x : i < 4 ? v.y : i < 6 ? v.z : v.w;
+        return (w >> (16 * (i & 1))) & 0xFFFFu;
+    }
+    __device__ static void set(T& v, int i, uint32_t x)
+    {
+        const uint32_t b = (x & 0xFFFFu) << (16 * (i & 1));
+        if (i < 2)
+            v.x |= b;
+        else if (i < 4)
+            v.y |= b;
+        else if (i < 6)
+            v.z |= b;
+        else
+            v.w |= b;
+    }
+};
+
 // SCAN: phase A's wave scan of long runs compiled in (section 3b)
 template <int PPT, int NB, int BK, bool SCAN>
 __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ records,
@@ -335,7 +378,7 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
     __shared__ double ktvs[CHUNK + 1];      // k (t - t_first) of the sorted records; then
     double* chg_S = ktvs;                 // change lists: S / (s_max - s_min) after the change
     __shared__ uint16_t chg_j[CHUNK + TILE];  // change lists: frame index in the segment
-    __shared__ __align__(8) uint16_t cnt[WAVES][TILE];
+    __shared__ __align__(16) uint16_t cnt[WAVES][TILE];
     // representative lane per (wave, pixel) and lane masks per wave for the
     // LDS stable rank (one and two pixels per thread; larger tiles, whose
     // threads hold more registers, use the ballot rank)
@@ -545,36 +588,40 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
                     rank[s] |= (uint32_t)jc[s] << 16;
             }
             // 2c. exclusive scan over (pixel, wave), pixel-major
+            // (each thread's PPT consecutive counters of a wave are read and
+            // written as one LDS access of 2 PPT bytes)
             {
-                uint32_t v[PPT][WAVES];
+                using Word = CounterWord<PPT>;
+                typename Word::T cw[WAVES];
                 uint32_t sum = 0;
 #pragma unroll
-                for (int i = 0; i < PPT; ++i)
+                for (int w = 0; w < WAVES; ++w) {
+                    cw[w] = reinterpret_cast<const typename Word::T*>(cnt[w])[tid];
 #pragma unroll
-                    for (int w = 0; w < WAVES; ++w) {
-                        v[i][w] = cnt[w][tid * PPT + i];
-                        sum += v[i][w];
-                    }
-                uint32_t inc = sum;
-#pragma unroll
-                for (int o = 1; o < kWave; o <<= 1) {
-                    const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
-                    if (lane >= o)
-                        inc += n;
+                    for (int i = 0; i < PPT; ++i)
+                        sum += Word::get(cw[w], i);
                 }
+                const uint32_t inc = wave_incl_sum(sum);
                 if (lane == kWave - 1)
                     scan_w[wave] = inc;
                 __syncthreads();
                 uint32_t run = inc - sum;
                 for (int w = 0; w < wave; ++w)
                     run += scan_w[w];
+                typename Word::T out[WAVES];
+#pragma unroll
+                for (int w = 0; w < WAVES; ++w)
+                    out[w] = typename Word::T{};
 #pragma unroll
                 for (int i = 0; i < PPT; ++i)
 #pragma unroll
                     for (int w = 0; w < WAVES; ++w) {
-                        cnt[w][tid * PPT + i] = (uint16_t)run;
-                        run += v[i][w];
+                        Word::set(out[w], i, run);
+                        run += Word::get(cw[w], i);
                     }
+#pragma unroll
+                for (int w = 0; w < WAVES; ++w)
+                    reinterpret_cast<typename Word::T*>(cnt[w])[tid] = out[w];
             }
             __syncthreads();
             // 2d. scatter into pixel order, the frame index over the pixel

@@ -214,25 +214,6 @@ __device__ __forceinline__ ClampAffine wave_scan(ClampAffine m)
     return m;
 }
 
-// Inclusive sum of the lanes' values in lane order, with the DPP steps of
-// wave_scan (lanes without a source add 0).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t src)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)src, CTRL, ROW_MASK, 0xF, false);
-}
-
-__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x)
-{
-    x += dpp_u32<0x111, 0xF>(x);  // row_shr:1
-    x += dpp_u32<0x112, 0xF>(x);  // row_shr:2
-    x += dpp_u32<0x114, 0xF>(x);  // row_shr:4
-    x += dpp_u32<0x118, 0xF>(x);  // row_shr:8
-    x += dpp_u32<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
-    x += dpp_u32<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
-    return x;
-}
-
 // Lane l's double, read by the whole wave (l uniform).
 __device__ __forceinline__ double readlane_f64(double v, int l)
 {

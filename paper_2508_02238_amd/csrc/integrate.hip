@@ -601,7 +601,13 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
                     for (int i = 0; i < PPT; ++i)
                         sum += Word::get(cw[w], i);
                 }
-                const uint32_t inc = wave_incl_sum(sum);
+                uint32_t inc = sum;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const uint32_t n = (uint32_t)__shfl_up((int)inc, o);
+                    if (lane >= o)
+                        inc += n;
+                }
                 if (lane == kWave - 1)
                     scan_w[wave] = inc;
                 __syncthreads();

@@ -157,6 +157,20 @@ def test_unsorted_input_state(esi):
     assert diag["flags"] & 1 and o.unsorted
 
 
+@pytest.mark.parametrize("W,H,n", [(346, 260, 400_000), (1280, 720, 2_000_000)])
+def test_unsorted_input_with_frames(esi, W, H, n):
+    """Unsorted times with frames requested (one and two pixels per thread,
+    many chunks and frame segments): the state is still that of array order,
+    and the frames, whose values are unspecified, stay finite in [0, 1]."""
+    s = evgen.random_stream(seed=31, width=W, height=H, n=n, t_max=2_000_000, sorted_=False)
+    tf = np.arange(1, 41, dtype=np.int64) * 50_000
+    fg, _, stg, diag = gpu_run(esi, s, DEFAULT, t_frames=tf)
+    _, o = oracle_run(s, DEFAULT, t_frames=None)
+    assert_state(stg, o, DEFAULT["C"], f"unsorted {W}x{H}")
+    assert diag["flags"] & 1 and o.unsorted
+    assert np.isfinite(fg).all() and fg.min() >= 0.0 and fg.max() <= 1.0
+
+
 def test_window_split_and_fps(esi):
     """One call vs many calls: exact N, P, T and S within tolerance; 100 and
     1000 FPS frames agree at the shared times."""

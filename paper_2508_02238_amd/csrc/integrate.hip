@@ -102,8 +102,9 @@ struct Pixels {
     // state after every event applied so far (Alg. 2)
     double S[PPT];
     int64_t T[PPT];
-    uint32_t N[PPT];  // events of this call (added to the stored count at the end)
-    int32_t P[PPT];   // their polarity sum
+    uint32_t N[PPT];  // this call's events (plus the stored count if loaded early)
+    int32_t P[PPT];   // their polarity sum, likewise
+    uint32_t touched; // bit i: pixel slot i has events in this call
     // the state the frames see: Sv = S / (s_max - s_min) and Av = 1 + k (T - t_b)
     // (exponential decay: Av = exp(k (T - t_b)))
     double Sv[PPT], Av[PPT];
@@ -353,8 +354,13 @@ struct CounterWord<8> {
     }
 };
 
-// SCAN: phase A's wave scan of long runs compiled in (section 3b)
-template <int PPT, int NB, int BK, bool SCAN>
+// SCAN: phase A's wave scan of long runs compiled in (section 3b).
+// EARLY_NP: N and P are loaded with S and T at the start of the tile, so that
+// its end waits for no load (batched calls, whose workgroups go on to the
+// next tile, and the larger tiles); otherwise they are read and updated at the
+// write-back (one pixel per thread, one tile per workgroup: loading them
+// first only lengthens the first wait).
+template <int PPT, int NB, int BK, bool SCAN, bool EARLY_NP>
 __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ records,
                                                const uint32_t* __restrict__ table,
                                                const uint32_t* __restrict__ total,
@@ -402,14 +408,15 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
 
     Pixels<PPT> px;
     bool in[PPT];
+    px.touched = 0u;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int64_t q = q0 + (int64_t)i * NB;
         in[i] = q < npix;
         px.S[i] = in[i] ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
         px.T[i] = in[i] ? st.T[q] : 0;
-        px.N[i] = 0u;  // this call's events and polarity sum; added to N, P at the end
-        px.P[i] = 0;
+        px.N[i] = (EARLY_NP && in[i]) ? st.N[q] : 0u;
+        px.P[i] = (EARLY_NP && in[i]) ? st.P[q] : 0;
     }
 
     // the tile's records [rs, re)
@@ -739,6 +746,7 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
                 px.S[i] = S;
                 px.N[i] += end - beg;
                 px.P[i] += (int32_t)(end - beg) - 2 * (int32_t)nneg;
+                px.touched |= (end > beg ? 1u : 0u) << i;
                 chg_j[w + l] = 0xFFFF;  // end of the list
                 // the first change's frame; eo at its entry, jo at the frame
                 // index after it
@@ -821,6 +829,7 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
                         px.T[i] = t_last;
                         px.N[i] += end - beg;
                         px.P[i] += (int32_t)(end - beg) - 2 * (int32_t)nneg;
+                        px.touched |= 1u << i;
                         chg_j[w + l] = 0xFFFF;
                         px.jn[i] = chg_j[beg + l];
                         px.eo[i] = 8u * beg;
@@ -861,13 +870,13 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
         const int64_t q = q0 + (int64_t)i * NB;
         // a pixel without events in this call keeps its stored state as it
         // is (S, T unchanged, no re-rounding), so only touched pixels write
-        if (in[i] && px.N[i] != 0u) {
+        if (in[i] && ((px.touched >> i) & 1u)) {
             const float hi = (float)px.S[i];
             st.S_hi[q] = hi;
             st.S_lo[q] = (float)(px.S[i] - (double)hi);
             st.T[q] = px.T[i];
-            st.N[q] += px.N[i];
-            st.P[q] += px.P[i];
+            st.N[q] = EARLY_NP ? px.N[i] : st.N[q] + px.N[i];
+            st.P[q] = EARLY_NP ? px.P[i] : st.P[q] + px.P[i];
         }
     }
     if (bad)
@@ -893,8 +902,9 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrat
     DiagDev* diag)
 {
     const int tile = order ? (int)load_const(order, blockIdx.x) : (int)blockIdx.x;
-    integrate_body<PPT, NB, BK, SCAN>(records, table, total, ev_t, K, st, mp, fo, diag, tile,
-                                      tile_bounds(table, total, ev_t, K, tile));
+    integrate_body<PPT, NB, BK, SCAN, (PPT >= 2)>(records, table, total, ev_t, K, st, mp, fo,
+                                                  diag, tile,
+                                                  tile_bounds(table, total, ev_t, K, tile));
 }
 
 // Batched: the tiles of items [i0, i1) (one tile size and decay kind), work
@@ -929,9 +939,9 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void kb_integra
         }
         const BatchItem& it = b.items[i];
         const int tile = (int)(w - first);
-        integrate_body<PPT, NB, BK, SCAN>(it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K,
-                                          it.st, it.mp, it.fo, it.diag, tile,
-                                          tile_bounds(it.cs.table, it.cs.total, it.ev.t, it.K, tile));
+        integrate_body<PPT, NB, BK, SCAN, true>(
+            it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K, it.st, it.mp, it.fo, it.diag,
+            tile, tile_bounds(it.cs.table, it.cs.total, it.ev.t, it.K, tile));
         __syncthreads();  // LDS is reused by the next tile
     }
 }

@@ -694,6 +694,8 @@ def bench_served(args) -> int:
         i = 0
         n_done = 0
         admitted_sum = ticks = 0
+        tick_host = 0.0   # host seconds inside the ticks that launched
+        host = dict(open=0.0, submit=0.0, tick=0.0, poll=0.0, close=0.0)  # host seconds per call kind
         while n_done < n_arr:
             now = time.perf_counter() - t_start
             if now > args.serve_s + 120.0:
@@ -706,24 +708,36 @@ def bench_served(args) -> int:
                 sid = (s, r)
                 if k == 0:
                     st = streams[s]
+                    th = time.perf_counter()
                     if srv.open(sid, st.width, st.height, **prm) == "rejected":
                         raise RuntimeError(f"session of {st.width}x{st.height} exceeds the "
                                            f"{args.budget_gb:g} GiB budget")
+                    host["open"] += time.perf_counter() - th
                     remaining[sid] = nwin
                 o, n = int(pk_off[s, k]), int(pk_n[s, k])
+                th = time.perf_counter()
                 srv.submit_device(sid, px + 2 * o, py + 2 * o, pt + 8 * o, pp + o, n,
                                   (k + 1) * win_us - 1, pid=k, arrival=t_start + a_t[i])
+                host["submit"] += time.perf_counter() - th
                 i += 1
+            th = time.perf_counter()
             if srv.tick():
                 ticks += 1
                 admitted_sum += len(srv.order)
-            for c in srv.poll():
+                tick_host += time.perf_counter() - th
+            host["tick"] += time.perf_counter() - th
+            th = time.perf_counter()
+            polled = srv.poll()
+            host["poll"] += time.perf_counter() - th
+            for c in polled:
                 n_done += 1
                 s, r = c.sid
                 done_events += int(pk_n[s, c.pid])
                 remaining[c.sid] -= 1
                 if remaining[c.sid] == 0:
+                    th = time.perf_counter()
                     srv.close(c.sid)
+                    host["close"] += time.perf_counter() - th
             if i >= n_arr:
                 # arrivals over: sessions cut short by the window close once drained
                 for sid, left in list(remaining.items()):
@@ -744,7 +758,12 @@ def bench_served(args) -> int:
              "p99_ms": round(float(np.percentile(lat, 99)), 3),
              "packets": int(lat.size), "wall_s": round(wall, 3),
              "mean_admitted_sessions": round(admitted_sum / max(ticks, 1), 1),
-             "mean_packets_per_tick": round(n_arr / max(ticks, 1), 1)}
+             "mean_packets_per_tick": round(n_arr / max(ticks, 1), 1),
+             "ticks_per_s": round(ticks / wall, 1),
+             "host_ms_per_tick": round(tick_host / max(ticks, 1) * 1e3, 3),
+             "host_s": {k: round(v, 3) for k, v in host.items()},
+             "states_created": getattr(srv, "created", None),
+             "states_destroyed": getattr(srv, "destroyed", None)}
         log(f"[bench] served {load:g} Gev/s offered: {r}")
         results.append(r)
     out = {

@@ -21,8 +21,11 @@ pixel), its frame ring (4 bytes per pixel per slot) and the most scratch the
 library allocates for its packets (esi_scratch_bound); a session that does
 not fit waits, in arrival order, until others close; one that could never fit
 is rejected.  Closed sessions' states are pooled and reused by sessions of
-the same size and parameters (creating and destroying a state synchronises
-the device).
+the same size and parameters: creating and destroying a state synchronises
+the device, which drains the ticks in flight.  So when the first waiting
+session would need pooled states of other kinds destroyed, a later waiting
+session whose kind has a pooled state is admitted first, at most
+``max_skip`` times in a row before the first one's turn is forced.
 
 The device side is an object with a small interface (``HipDevice`` on a GPU;
 the scheduling tests substitute a CPU double), so admission, fairness,
@@ -33,6 +36,7 @@ only; the other sessions go on.
 from __future__ import annotations
 
 import collections
+import itertools
 import time
 from dataclasses import dataclass
 
@@ -65,9 +69,13 @@ class Session:
         self.launched = 0      # packets launched so far (ring slot = launched % ring)
         self.inflight = 0      # packets in ticks not completed yet
         self.status = "new"    # waiting, admitted, failed, closing, closed, rejected
+        self.skipped = 0       # admissions of later sessions ahead of this one
+        self.seq = 0           # arrival number
+        self._key = (width, height, tuple(sorted(params.items())))
 
     def key(self):
-        return (self.width, self.height, tuple(sorted(self.params.items())))
+        """The kind of state the session needs: size and method parameters."""
+        return self._key
 
 
 class HipDevice:
@@ -188,9 +196,14 @@ class HipDevice:
             b["tfd"][:m].copy_(b["tf"][:m], non_blocking=True)
         self.compute.wait_stream(self.copy)
         ev = self._ev[:m]
-        for i, it in enumerate(items):
-            if it[4] is not None:
-                ev[i] = (*it[4], it[5]) if it[5] else (0, 0, 0, 0, 0)
+        devi = [i for i, it in enumerate(items) if it[4] is not None]
+        if devi:
+            dp = np.array([items[i][4] for i in devi], dtype=np.uint64).reshape(-1, 4)
+            nd = ns[devi].astype(np.uint64)
+            has = nd > 0
+            for j, f in enumerate(("x", "y", "t", "p")):
+                ev[f][devi] = np.where(has, dp[:, j], np.uint64(0))
+            ev["n"][devi] = nd
         if hosted:
             dx, dy, dt, dp = (d.data_ptr() for d in b["d"])
             o = offs[:-1].astype(np.uint64)
@@ -238,7 +251,7 @@ class Server:
     (default: HipDevice on the current GPU)."""
 
     def __init__(self, budget_bytes: int, max_batch: int = 256, max_packet_events: int = 1 << 20,
-                 ring: int = 3, max_inflight: int = 2, device=None):
+                 ring: int = 3, max_inflight: int = 2, device=None, max_skip: int = 8):
         if ring <= max_inflight:
             raise ValueError("ring must exceed max_inflight")
         self.budget = int(budget_bytes)
@@ -249,13 +262,21 @@ class Server:
         self.device = device if device is not None else HipDevice(max_batch, max_packet_events)
         self.used = 0
         self.sessions = {}
-        self.waiting = collections.deque()   # sessions not admitted yet, in arrival order
+        # sessions not admitted yet, in arrival order, all and per kind (entries
+        # whose status is no longer "waiting" are dropped when they reach the
+        # front)
+        self.waiting = collections.deque()
+        self.waiting_kind = {}
+        self.n_waiting = 0
+        self._arrivals = itertools.count()
         self.order = []                      # admitted sessions, round-robin order
         self.cursor = 0
         self.inflight = collections.deque()  # (token, [(session, pid, arrival, slot)])
         self.retiring = collections.deque()  # (token, session) closed, not released yet
         self.pool = collections.defaultdict(list)  # key -> [(state, frames)]
         self.done = []                       # every Completion so far
+        self.max_skip = int(max_skip)
+        self.created = self.destroyed = 0    # device states, for the record
 
     # ---- sessions ------------------------------------------------------
     def _cost(self, w, h):
@@ -267,16 +288,29 @@ class Server:
         if sid in self.sessions:
             raise KeyError(f"session {sid!r} exists")
         s = Session(sid, int(width), int(height), params, self._cost(width, height))
+        s.seq = next(self._arrivals)
         self.sessions[sid] = s
         if s.cost > self.budget:
             s.status = "rejected"
             return s.status
-        if not self.waiting and self._fits(s):
+        if not self.n_waiting and self._fits(s):
             self._admit(s)
         else:
             s.status = "waiting"
             self.waiting.append(s)
+            self.waiting_kind.setdefault(s.key(), collections.deque()).append(s)
+            self.n_waiting += 1
         return s.status
+
+    @staticmethod
+    def _first_waiting(q):
+        while q and q[0].status != "waiting":
+            q.popleft()
+        return q[0] if q else None
+
+    def _admit_waiting(self, s):
+        self.n_waiting -= 1
+        self._admit(s)
 
     def _admit(self, s):
         pooled = self.pool.get(s.key())
@@ -287,8 +321,13 @@ class Server:
         else:
             s.state, s.frames = self.device.create(s.width, s.height, s.params, self.ring)
             self.used += s.cost
+            self.created += 1
         s.status = "admitted"
         self.order.append(s)
+
+    def _fits_as_is(self, s) -> bool:
+        """Room for s without destroying pooled states."""
+        return bool(self.pool.get(s.key())) or self.used + s.cost <= self.budget
 
     def _fits(self, s) -> bool:
         """Room for s: a pooled state of its kind, free budget, or budget
@@ -301,6 +340,7 @@ class Server:
                 return False
             st, _ = self.pool[victim].pop()
             self.device.destroy(st)
+            self.destroyed += 1
             self.used -= self._cost(victim[0], victim[1])
         return True
 
@@ -314,8 +354,8 @@ class Server:
             self.done.append(Completion(sid, pk[0], -1, now - pk[1], False))
         s.pending.clear()
         if s.status in ("waiting", "rejected", "new"):
-            if s in self.waiting:
-                self.waiting.remove(s)
+            if s.status == "waiting":
+                self.n_waiting -= 1   # its queue entries are dropped lazily
             s.status = "closed"
             return
         if s.status == "failed":
@@ -345,13 +385,34 @@ class Server:
                 # a failed device call may have left the state poisoned:
                 # destroy it rather than pool it
                 self.device.destroy(s.state)
+                self.destroyed += 1
                 self.used -= s.cost
             else:
                 self.pool[s.key()].append((s.state, s.frames))
             s.state = s.frames = None
             s.status = "closed"
-        while self.waiting and self._fits(self.waiting[0]):
-            self._admit(self.waiting.popleft())
+        while self.n_waiting:
+            head = self._first_waiting(self.waiting)
+            if self._fits_as_is(head):
+                self._admit_waiting(head)
+                continue
+            if head.skipped < self.max_skip:
+                # the head needs pooled states of other kinds destroyed:
+                # admit first the earliest waiting session of a kind that
+                # has a pooled state
+                later = None
+                for key, states in self.pool.items():
+                    q = self.waiting_kind.get(key)
+                    c = self._first_waiting(q) if (states and q) else None
+                    if c is not None and (later is None or c.seq < later.seq):
+                        later = c
+                if later is not None:
+                    head.skipped += 1
+                    self._admit_waiting(later)
+                    continue
+            if not self._fits(head):
+                break
+            self._admit_waiting(head)
 
     def admitted(self, sid) -> bool:
         return self.sessions[sid].status == "admitted"

@@ -250,3 +250,33 @@ def test_killed_session_mid_stream():
     for sid in (0, 2, 3):
         assert [p[0] for p in srv.sessions[sid].state.packets] == [sid * 1000 + k for k in range(4)]
     srv.close_all()
+
+
+def test_admission_prefers_pooled_kind_with_bounded_skips():
+    """When the first waiting session would need pooled states of another
+    kind destroyed (a device-wide synchronisation on a GPU), a later waiting
+    session whose kind has a pooled state is admitted first, at most
+    max_skip times before the first one's turn is forced."""
+    dev = FakeDevice()
+    probe = Server(budget_bytes=1, device=dev)
+    ca, cb = probe._cost(16, 16), probe._cost(8, 8)
+    srv = Server(budget_bytes=2 * ca + cb // 2, max_batch=8, ring=3, device=dev, max_skip=2)
+    assert srv.open("a1", 16, 16) == "admitted" and srv.open("a2", 16, 16) == "admitted"
+    assert srv.open("b1", 8, 8) == "waiting"          # needs budget: behind nobody
+    for k in range(3, 7):
+        assert srv.open(f"a{k}", 16, 16) == "waiting"
+    created = srv.created
+    # a1 closes: its pooled state goes to a3, ahead of b1 (one skip)
+    srv.close("a1"); dev.run(); srv.poll()
+    assert srv.status("a3") == "admitted" and srv.status("b1") == "waiting"
+    assert srv.created == created and srv.destroyed == 0
+    # a2 closes: a4 takes its state (second skip of b1)
+    srv.close("a2"); dev.run(); srv.poll()
+    assert srv.status("a4") == "admitted" and srv.status("b1") == "waiting"
+    # a3 closes: b1 has been passed over twice, so its turn is forced: the
+    # pooled 16x16 state is destroyed to make room, and a5 keeps waiting
+    srv.close("a3"); dev.run(); srv.poll()
+    assert srv.status("b1") == "admitted" and srv.status("a5") == "waiting"
+    assert srv.destroyed == 1 and srv.created == created + 1
+    assert srv.used <= srv.budget
+    srv.close_all()

@@ -670,6 +670,23 @@ def bench_served(args) -> int:
     px, py, pt, pp = (a.data_ptr() for a in (xs, ys, ts, ps))
     results = []
     budget = int(args.budget_gb * (1 << 30))
+    # tile sizes per sensor size and the scan threshold from the autotuner
+    # over the first two packets of every stream (throwaway states; not
+    # timed), applied to every state the server creates
+    from paper_2508_02238_amd.serve import HipDevice
+    from paper_2508_02238_amd.tune import tune
+    h0 = time.time()
+    sample = []
+    for k in range(2):
+        evs = []
+        for i in range(n_sess):
+            lo, hi = int(pk_off[i, k]), int(pk_off[i, k] + pk_n[i, k])
+            evs.append((xs[lo:hi], ys[lo:hi], ts[lo:hi], ps[lo:hi]))
+        tfk = torch.tensor([(k + 1) * win_us - 1], dtype=torch.int64, device=dev)
+        sample.append((evs, [tfk] * n_sess))
+    tuned = tune([(s.width, s.height) for s in streams], prm, sample)
+    log(f"[bench] tuned tile pixels {tuned['tile_pixels']}, scan run {tuned['scan_run']} "
+        f"({time.time() - h0:.1f} s)")
     for load in args.loads:
         f = load * 1e9 / rate_1x
         rng = np.random.default_rng(5)
@@ -684,8 +701,10 @@ def bench_served(args) -> int:
         s_idx = np.broadcast_to(np.arange(n_sess)[:, None], at.shape)[sel][order]
         j_idx = np.broadcast_to(np.arange(per)[None, :], at.shape)[sel][order]
         a_t = at[sel][order]
+        device = HipDevice(args.max_batch, max_pk, tile_pixels=tuned["tile_pixels"],
+                           scan_run=tuned["scan_run"])
         srv = Server(budget_bytes=budget, max_batch=args.max_batch, max_packet_events=max_pk,
-                     ring=3, max_inflight=2)
+                     ring=3, max_inflight=2, device=device)
         remaining = {}
         done_events = 0
         n_arr = len(a_t)
@@ -780,7 +799,9 @@ def bench_served(args) -> int:
                                f"packets, Poisson arrivals, {args.budget_gb:g} GiB HBM budget, "
                                f"packets resident in device memory",
                    "sessions": n_sess, "packets_per_pass": nwin, "params": prm,
-                   "budget_gib": args.budget_gb, "max_batch": args.max_batch},
+                   "budget_gib": args.budget_gb, "max_batch": args.max_batch,
+                   "tile_pixels": {f"{w}x{h}": t for (w, h), t in tuned["tile_pixels"].items()},
+                   "scan_run": tuned["scan_run"]},
         "loads": results,
     }
     print(json.dumps(out), flush=True)

@@ -83,7 +83,11 @@ class HipDevice:
     current torch device); every step of the method runs in libesi's
     kernels through esi_integrate_batch."""
 
-    def __init__(self, max_batch: int, max_packet_events: int):
+    def __init__(self, max_batch: int, max_packet_events: int, tile_pixels=None,
+                 scan_run: int = 0):
+        """tile_pixels: {(W, H): integration tile size} for the states it
+        creates (the autotuner's choice; sizes not listed keep the library's
+        default); scan_run: their serial-versus-scan run length (0: default)."""
         import torch
 
         from . import Batch, esi_events
@@ -93,6 +97,8 @@ class HipDevice:
         self.copy = torch.cuda.Stream(self.dev)   # default priority
         self.max_batch = int(max_batch)
         self.max_packet_events = int(max_packet_events)
+        self.tile_pixels = dict(tile_pixels or {})
+        self.scan_run = int(scan_run)
         self.batch = Batch(self.max_batch)
         self._bufs = [None, None]
         self._flip = 0
@@ -122,6 +128,10 @@ class HipDevice:
         with torch.cuda.stream(self.compute):
             st = State(w, h, **params)
             frames = torch.empty((ring, h, w), dtype=torch.float32, device=self.dev)
+        if (w, h) in self.tile_pixels:
+            st.set_tile_pixels(self.tile_pixels[(w, h)])
+        if self.scan_run:
+            st.set_scan_run(self.scan_run)
         return st, frames
 
     def reset(self, st):

@@ -72,9 +72,13 @@ def _serve(srv, streams, packets_of, n_packets):
     return {sid: [frames[sid][k] for k in range(n_packets)] for sid in streams}, states
 
 
-def _alone(esi, w, h, prm, packets):
+def _alone(esi, w, h, prm, packets, tile_pixels=0, scan_run=0):
     import torch
     st = esi.State(w, h, **prm)
+    if tile_pixels:
+        st.set_tile_pixels(tile_pixels)
+    if scan_run:
+        st.set_scan_run(scan_run)
     frs = []
     for ws, tf in packets:
         fr, _ = st.integrate(ws.x, ws.y, ws.t, ws.p, t_frames=np.array([tf], np.int64))
@@ -186,3 +190,33 @@ def test_served_growing_packets(esi):
             assert torch.equal(a, b), i
         for k in range(len(sizes)):
             assert torch.equal(frames[i][k], frs[k]), (i, k)
+
+
+def test_served_with_tuned_tiles(esi):
+    """States created with the autotuner's kind of choice (1024-pixel tiles,
+    scan above 16 events) serve every session as it integrates alone with
+    the same settings, bit for bit, and match the FP64 oracle."""
+    import torch
+    from paper_2508_02238_amd.serve import HipDevice, Server
+    prm = dict(C=0.2, k_per_us=2e-5, b=2.0, s_min=-1.0, s_max=1.0)
+    sizes = SIZES[:6]
+    streams = {i: _stream(40 + i, w, h) for i, (w, h) in enumerate(sizes)}
+    device = HipDevice(4, 1 << 14, tile_pixels={sz: 1024 for sz in sizes}, scan_run=16)
+    srv = Server(budget_bytes=1 << 40, max_batch=4, max_packet_events=1 << 14, device=device)
+    for i, (w, h) in enumerate(sizes):
+        assert srv.open(i, w, h, **prm) == "admitted"
+    got_frames, got_states = _serve(srv, streams, lambda sid, k: _packet(streams[sid], k),
+                                    PACKETS)
+    srv.close_all()
+    tf_all = np.array([(k + 1) * PACKET_US - 1 for k in range(PACKETS)], np.int64)
+    for i, (w, h) in enumerate(sizes):
+        pk = [_packet(streams[i], k) for k in range(PACKETS)]
+        frs, ref = _alone(esi, w, h, prm, pk, tile_pixels=1024, scan_run=16)
+        for a, b in zip(got_states[i], ref):
+            assert torch.equal(a, b), i
+        for k in range(PACKETS):
+            assert torch.equal(got_frames[i][k], frs[k]), (i, k)
+        fo, o = oracle_run(streams[i], prm, t_frames=tf_all)
+        S, T, N, P = (a.cpu().numpy() for a in got_states[i])
+        assert_state((S, T, N.view(np.uint32), P), o, prm["C"], f"tuned {i}")
+        assert_frames(torch.stack(got_frames[i]).cpu().numpy(), fo, prm, f"tuned {i}")

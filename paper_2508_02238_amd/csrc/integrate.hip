@@ -285,11 +285,13 @@ __device__ __forceinline__ ChunkCtl chunk_ctl(const uint64_t* records, uint32_t 
 
 // One pixel per thread: five workgroups per CU (at most 96 VGPRs, 32 KB of
 // LDS each), so that a 640x480 sensor's 1200 tiles are all resident at once.
-// Two pixels per thread: four (at most 128 VGPRs, 40 KB).  (Tiles of 512
-// pixels as 512 threads x 1 pixel ran 7% slower than 256 x 2 on the
-// 1280x720 spoke workload: two workgroups per CU, eight-wave barriers.)
+// Two pixels per thread: four (at most 128 VGPRs, 40 KB).  Four pixels: two
+// (at most 256 VGPRs; the batched kernel holds the next tile's state besides
+// its own).  (Tiles of 512 pixels as 512 threads x 1 pixel ran 7% slower than
+// 256 x 2 on the 1280x720 spoke workload: two workgroups per CU, eight-wave
+// barriers.)
 template <int PPT, int NB>
-constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : PPT == 2 ? 4 : 1; }
+constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : PPT == 2 ? 4 : PPT == 4 ? 2 : 1; }
 
 // A tile's record window [rs, re) in its bucket and the call's time origin
 // (scalar loads; a batched workgroup loads the next tile's while it works on
@@ -354,19 +356,53 @@ struct CounterWord<8> {
     }
 };
 
+// One tile's stored state (S as its FP32 pair, T, N, P) per pixel slot,
+// loaded by the batched kernel while the previous tile finishes.
+template <int PPT>
+struct TileState {
+    float s_hi[PPT], s_lo[PPT];
+    int64_t T[PPT];
+    uint32_t N[PPT];
+    int32_t P[PPT];
+};
+
+template <int PPT, int NB>
+__device__ __forceinline__ void load_tile_state(const StateDev& st, int tile, TileState<PPT>& ts)
+{
+    const int64_t q0 = (int64_t)tile * (NB * PPT) + threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int64_t q = q0 + (int64_t)i * NB;
+        const bool in = q < st.npix;
+        ts.s_hi[i] = in ? st.S_hi[q] : 0.0f;
+        ts.s_lo[i] = in ? st.S_lo[q] : 0.0f;
+        ts.T[i] = in ? st.T[q] : 0;
+        ts.N[i] = in ? st.N[q] : 0u;
+        ts.P[i] = in ? st.P[q] : 0;
+    }
+}
+
+// No state loaded ahead: the body loads its own.
+struct NoPrefetch {
+    __device__ void operator()() const {}
+};
+
 // SCAN: phase A's wave scan of long runs compiled in (section 3b).
 // EARLY_NP: N and P are loaded with S and T at the start of the tile, so that
 // its end waits for no load (batched calls, whose workgroups go on to the
 // next tile, and the larger tiles); otherwise they are read and updated at the
 // write-back (one pixel per thread, one tile per workgroup: loading them
 // first only lengthens the first wait).
-template <int PPT, int NB, int BK, bool SCAN, bool EARLY_NP>
+template <int PPT, int NB, int BK, bool SCAN, bool EARLY_NP, bool PRE = false,
+          typename Next = NoPrefetch>
 __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ records,
                                                const uint32_t* __restrict__ table,
                                                const uint32_t* __restrict__ total,
                                                const int64_t* __restrict__ ev_t, int K,
                                                StateDev st, MethodParams mp, FrameOut fo,
-                                               DiagDev* diag, int tile, const TileBounds& tb)
+                                               DiagDev* diag, int tile, const TileBounds& tb,
+                                               const TileState<PPT>* pre = nullptr,
+                                               Next next = Next{})
 {
     using Cfg = TileCfg<PPT, NB>;
     constexpr int TILE = Cfg::TILE;
@@ -413,10 +449,17 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
     for (int i = 0; i < PPT; ++i) {
         const int64_t q = q0 + (int64_t)i * NB;
         in[i] = q < npix;
-        px.S[i] = in[i] ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
-        px.T[i] = in[i] ? st.T[q] : 0;
-        px.N[i] = (EARLY_NP && in[i]) ? st.N[q] : 0u;
-        px.P[i] = (EARLY_NP && in[i]) ? st.P[q] : 0;
+        if constexpr (PRE) {
+            px.S[i] = (double)pre->s_hi[i] + (double)pre->s_lo[i];
+            px.T[i] = pre->T[i];
+            px.N[i] = pre->N[i];
+            px.P[i] = pre->P[i];
+        } else {
+            px.S[i] = in[i] ? (double)st.S_hi[q] + (double)st.S_lo[q] : 0.0;
+            px.T[i] = in[i] ? st.T[q] : 0;
+            px.N[i] = (EARLY_NP && in[i]) ? st.N[q] : 0u;
+            px.P[i] = (EARLY_NP && in[i]) ? st.P[q] : 0;
+        }
     }
 
     // the tile's records [rs, re)
@@ -847,6 +890,11 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
         // drains the frame stores of the previous segment (one counter covers
         // loads and stores), which have had the whole sort to complete.
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        // the next tile's state, loaded during this tile's last frames
+        if constexpr (PRE) {
+            if (!(ce < re || j_end < nf))
+                next();
+        }
         // 4. phase B: the frames this chunk completes
         if (nfw > 0) {
             const size_t base = (size_t)j * (size_t)fo.stride + (size_t)tile * TILE;
@@ -931,6 +979,11 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void kb_integra
     }
     int i = lo;
     uint32_t first = load_const(b.tile_base, i), next = load_const(b.tile_base, i + 1);
+    // the larger tiles load each next tile's state while the current one
+    // finishes (its last frames and write-back)
+    constexpr bool kPre = PPT >= 4;
+    TileState<PPT> cur, nxt;
+    bool have = false;
     for (; w < w_end; ++w) {
         while (w >= next) {
             ++i;
@@ -939,9 +992,40 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void kb_integra
         }
         const BatchItem& it = b.items[i];
         const int tile = (int)(w - first);
-        integrate_body<PPT, NB, BK, SCAN, true>(
-            it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K, it.st, it.mp, it.fo, it.diag,
-            tile, tile_bounds(it.cs.table, it.cs.total, it.ev.t, it.K, tile));
+        if constexpr (kPre) {
+            if (!have)
+                load_tile_state<PPT, NB>(it.st, tile, cur);
+            // the tile after this one: its item and index
+            const bool more = w + 1 < w_end;
+            int i2 = i;
+            uint32_t f2 = first;
+            if (more && w + 1 >= next) {
+                i2 = i + 1;
+                f2 = next;
+                while (w + 1 >= load_const(b.tile_base, i2 + 1)) {
+                    ++i2;
+                    f2 = load_const(b.tile_base, i2);
+                }
+            }
+            bool loaded = false;
+            auto prefetch = [&]() {
+                if (more) {
+                    load_tile_state<PPT, NB>(b.items[i2].st, (int)(w + 1 - f2), nxt);
+                    loaded = true;
+                }
+            };
+            integrate_body<PPT, NB, BK, SCAN, true, true>(
+                it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K, it.st, it.mp, it.fo,
+                it.diag, tile, tile_bounds(it.cs.table, it.cs.total, it.ev.t, it.K, tile), &cur,
+                prefetch);
+            if (loaded)
+                cur = nxt;
+            have = loaded;
+        } else {
+            integrate_body<PPT, NB, BK, SCAN, true>(
+                it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K, it.st, it.mp, it.fo,
+                it.diag, tile, tile_bounds(it.cs.table, it.cs.total, it.ev.t, it.K, tile));
+        }
         __syncthreads();  // LDS is reused by the next tile
     }
 }

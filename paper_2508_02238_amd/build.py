@@ -20,6 +20,8 @@ HIPCC_FLAGS = [
     "-Xarch_device", "-fno-honor-nans",
     "-Wall", "-Wno-unused-result",
 ]
+# named host ranges for profilers (roctx, ROCm's rocprofiler-sdk)
+LINK_FLAGS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def sources():
@@ -29,7 +31,7 @@ def sources():
 def build(out: str = LIB, verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(PKG, "csrc"), "-o", out + ".tmp", *sources()]
+           "-I", os.path.join(PKG, "csrc"), "-o", out + ".tmp", *sources(), *LINK_FLAGS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,6 +1,7 @@
 // api.hip -- the C ABI declared in include/esi.h: argument checks, state and
 // scratch ownership, the per-call schedule, and stream-ordered launches.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -14,6 +15,21 @@
 #include "esi_internal.hpp"
 
 using namespace esi;
+
+namespace {
+
+// A named range on the calling thread for profilers (rocprofv3
+// --marker-trace): the host time of an entry point and of each launch phase
+// it enqueues.  The phases' GPU time is measured with HIP events instead
+// (esi_profile_enable).
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+
+}  // namespace
 
 // A pixel's run of more than this many events in one chunk of its tile is
 // integrated by the scan of the whole wave rather than by one lane: below it
@@ -479,6 +495,7 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
         return ESI_ERR_INVALID_ARG;
     if (st->poisoned)
         return ESI_ERR_POISONED;
+    Range range(static_scratch ? "esi_integrate_window_noalloc" : "esi_integrate_window");
     DeviceGuard g(st->device);
     const int64_t n = (int64_t)ev->n;
     MethodParams mp = method_params(st->params);
@@ -531,12 +548,16 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
         const int64_t off = y0 * st->W;
         const FrameOut fo{tf, n_frames, frames ? frames + off : nullptr,
                           frames_u8 ? frames_u8 + off : nullptr, st->npix};
-        if (n > 0 && launch_bucket(evd, sd, sc, cs, st->diag, stream) != hipSuccess)
-            return hip_fail(st);
+        if (n > 0) {
+            Range phase("bucketing");
+            if (launch_bucket(evd, sd, sc, cs, st->diag, stream) != hipSuccess)
+                return hip_fail(st);
+        }
         // the bucketing time of a banded call is its first band's
         if (pe && y0 == 0 && hipEventRecord(pe[1], stream) != hipSuccess)
             return hip_fail(st);
         if (n > 0 || n_frames > 0) {
+            Range phase("integration");
             mp.scan_run = effective_scan_run(st->scan_run, sc.ppt);
             if (launch_integrate(evd, sd, sc, cs, mp, fo, st->diag, stream) != hipSuccess)
                 return hip_fail(st);
@@ -573,6 +594,7 @@ esi_status esi_snapshot_frame(esi_state* st, int64_t t_frame_us, float* frame, u
         return ESI_ERR_INVALID_ARG;
     if (st->poisoned)
         return ESI_ERR_POISONED;
+    Range range("esi_snapshot_frame");
     DeviceGuard g(st->device);
     if (launch_snapshot(st->dev, method_params(st->params), t_frame_us, frame, u8, stream) !=
         hipSuccess)
@@ -856,6 +878,7 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
     for (int32_t i = 0; i < n_items; ++i)
         if (states[i]->poisoned)
             return ESI_ERR_POISONED;
+    Range range("esi_integrate_batch");
     DeviceGuard g(b->device);
 
     // schedules: the bucketing ranges shared out by event count
@@ -979,8 +1002,12 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         hipEventRecord(b->copied, stream) != hipSuccess)
         return fail();
     b->pending = true;
-    if (n_all > 0 && launch_bucket_batch(bd, ub[n_items], sb[n_items], kmax, stream) != hipSuccess)
-        return fail();
+    if (n_all > 0) {
+        Range phase("bucketing");
+        if (launch_bucket_batch(bd, ub[n_items], sb[n_items], kmax, stream) != hipSuccess)
+            return fail();
+    }
+    Range phase("integration");
     for (int32_t k0 = 0; k0 < n_items;) {
         int32_t k1 = k0 + 1;
         while (k1 < n_items && cls[order[k1]] == cls[order[k0]])

@@ -33,6 +33,15 @@ def test_library_exports_every_declared_symbol():
     assert set(esi.EXPORTED) == set(_declared())
 
 
+def test_library_marks_its_phases_for_profilers():
+    # entry points and launch phases are named host ranges (roctx), which
+    # rocprofv3 --marker-trace records
+    import paper_2508_02238_amd as esi
+    out = subprocess.run(["nm", "-D", "--undefined-only", esi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+
+
 def test_status_strings():
     import paper_2508_02238_amd as esi
     for s in range(6):

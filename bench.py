@@ -114,7 +114,7 @@ def _sources_hash(sources) -> str:
 
 
 def _short_kernel_name(name: str) -> str:
-    """k_bucket<4096> from 'void esi::(anonymous namespace)::k_bucket<4096>(...)'."""
+    """k_bucket<8192, 8> from 'void esi::(anonymous namespace)::k_bucket<8192, 8>(...)'."""
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
     return name.split("(")[0].replace("esi::", "")
 

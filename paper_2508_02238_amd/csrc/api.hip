@@ -62,7 +62,7 @@ struct esi_state {
     // device address of the static scratch on this state's device (null if
     // the lookup failed: esi_integrate_window_noalloc then returns ESI_ERR_HIP)
     void* static_scratch = nullptr;
-    int bucket_slots = 1024;  // bucketing workgroups resident at once
+    int bucket_slots[2] = {1024, 1024};  // bucketing workgroups resident at once (narrow, wide)
     int integ_slots[4] = {1 << 30, 1 << 30, 1 << 30, 1 << 30};  // per ppt 1, 2, 4, 8
     int min_ppt = 1;          // smallest pixels per thread of the integration tiles
     int scan_run = 0;  // longer runs per chunk take the wave's scan (0: by tile size)
@@ -380,8 +380,8 @@ esi_status esi_create_state(int32_t width, int32_t height, const esi_params* par
     st->dev.H = height;
     st->dev.npix = npix;
     st->diag = (DiagDev*)(base + o_diag);
-    st->bucket_slots =
-        bucket_slots(make_schedule(band_rows(width, height) * width, 0, 1).ntiles);
+    st->bucket_slots[0] = bucket_slots(1);
+    st->bucket_slots[1] = bucket_slots(kMaxTiles);
     st->static_scratch = static_scratch_address(st->device);
     for (int i = 0; i < 4; ++i)
         st->integ_slots[i] = integrate_slots(1 << i);
@@ -506,7 +506,11 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
     // largest, so its scratch serves every band
     const int64_t rows = band_rows(st->W, st->H);
     const bool stage_tf = n_frames > 0 && !device_accessible(t_frames);
-    const Schedule sc0 = make_schedule(rows * st->W, n, st->bucket_slots, st->min_ppt);
+    // ranges: the resident workgroups of the bucketing form the call's tile
+    // count selects (the tile count does not depend on the ranges)
+    const int slots =
+        st->bucket_slots[bucket_wide(make_schedule(rows * st->W, n, 1, st->min_ppt).ntiles)];
+    const Schedule sc0 = make_schedule(rows * st->W, n, slots, st->min_ppt);
     CallScratch cs{};
     int64_t* tf_dev = nullptr;
     if (static_scratch) {
@@ -543,7 +547,7 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
         const int64_t hb = std::min<int64_t>(rows, st->H - y0);
         const StateDev sd = band_state(st->dev, y0, hb);
         const Schedule sc =
-            make_schedule(sd.npix, n, st->bucket_slots, st->min_ppt, st->integ_slots);
+            make_schedule(sd.npix, n, slots, st->min_ppt, st->integ_slots);
         const EventsDev evd{ev->x, ev->y, ev->t, ev->p, n, (int)y0, st->H};
         const int64_t off = y0 * st->W;
         const FrameOut fo{tf, n_frames, frames ? frames + off : nullptr,
@@ -735,7 +739,10 @@ esi_status esi_scratch_bound(int32_t width, int32_t height, size_t n_events, siz
     // the most bucketing ranges any call gives one state: the resident
     // bucketing workgroups of the smallest tile table
     const int64_t npix = band_rows(width, height) * width;
-    const Schedule sc = make_schedule(npix, (int64_t)n_events, bucket_slots(1));
+    // the larger range count of the two bucketing kernels (more ranges, a
+    // larger table)
+    const Schedule sc = make_schedule(npix, (int64_t)n_events,
+                                      std::max(bucket_slots(1), bucket_slots_batch(1)));
     const ScratchPlan p = scratch_plan(sc, (int64_t)n_events, 0);
     *bytes = n_events > 0 ? p.need + p.need / 4 : 0;  // with the growth margin of call_scratch
     return ESI_OK;
@@ -889,7 +896,7 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         if (events[i].n > 0)
             kmax = std::max(kmax, sc[i].ntiles);
     }
-    const int slots = bucket_slots(kmax);
+    const int slots = bucket_slots_batch(kmax);
     std::vector<BatchItem> it(n_items);
     std::vector<int> cls(n_items);  // integration class: tile size and decay kind
     for (int32_t i = 0; i < n_items; ++i) {

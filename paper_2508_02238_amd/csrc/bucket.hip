@@ -17,7 +17,7 @@
 //               per-tile sums over segments of ranges (and per-tile totals),
 //               then each segment rescanned into offsets.
 //   k_bucket    per range again, in sub-batches of SUB events: each wave ranks
-//               its quarter of the sub-batch stably by tile (wave-wide key
+//               its share of the sub-batch stably by tile (wave-wide key
 //               match), a scan over (tile, wave) gives every event its place
 //               in the sub-batch sorted by tile, the 64-bit records (time
 //               offset, pixel in tile, polarity) are staged in LDS in that
@@ -42,7 +42,15 @@ namespace {
 
 constexpr int kXcds = 8;
 constexpr int kSegRows = 16;  // table rows (ranges) per segment of the column scan
-constexpr int kSub = 4096;    // events per sub-batch of k_bucket
+// Sub-batches of the bucketing: 4096 events over four waves (two workgroups
+// per CU), and for calls of kWideTiles tiles or more 8192 events over eight
+// waves (one workgroup per CU): twice the run per tile and write-out, and the
+// per-sub-batch scan over the tiles spread over twice the events.  The
+// batched kernel always takes the first.
+constexpr int kSub = 4096;
+constexpr int kSubWide = 8192;
+constexpr int kWavesWide = 8;
+constexpr int kWideTiles = 1536;
 
 // Bijection blockIdx -> work index that gives each XCD a contiguous range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
@@ -219,39 +227,41 @@ __device__ __forceinline__ void seg_down_body(uint32_t* table, int K, int64_t B,
 
 // ---- stable bucketing, staged in LDS ------------------------------------------
 
-template <int SUB>
+template <int SUB, int NW>
 __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, int tile_log, int K,
                                             int64_t E, const uint32_t* table, uint64_t* records,
                                             int64_t cap, DiagDev* diag, int64_t unit)
 {
-    constexpr int PER_WAVE = SUB / kWavesPerBlock;  // events per wave per sub-batch
+    constexpr int NT = NW * kWave;                  // threads of the workgroup
+    constexpr int CW = NW / 4;                      // 64-bit counter words per tile
+    static_assert(NW % 4 == 0, "four 16-bit wave counters per word");
+    constexpr int PER_WAVE = SUB / NW;              // events per wave per sub-batch
     constexpr int STEPS = PER_WAVE / kWave;         // steps of 64 per wave
     constexpr int BATCH = STEPS < 8 ? STEPS : 8;    // steps loaded ahead
     static_assert(STEPS % BATCH == 0, "sub-batch size");
-    static_assert(sizeof(uint64_t) * SUB >= sizeof(uint64_t) * kWavesPerBlock * kWave +
-                                                kWavesPerBlock * kMaxTiles,
+    static_assert(sizeof(uint64_t) * SUB >= sizeof(uint64_t) * NW * kWave + NW * kMaxTiles,
                   "the rank's scratch fits the staging area");
     extern __shared__ uint64_t smem[];
     // LDS: staged | cw | gbase | wd | skey.  While a sub-batch is ranked, the
     // staging area holds the rank's representative lanes and lane masks.
     uint64_t* staged = smem;                      // [SUB] records of the sub-batch by tile
-    uint64_t* cw = staged + SUB;                  // [K] 4 x u16: per-wave counters, then run starts
-    uint32_t* gbase = (uint32_t*)(cw + K);        // [K] next bucket position of each tile
+    uint64_t* cw = staged + SUB;                  // [K][CW] NW x u16: per-wave counters, then run starts
+    uint32_t* gbase = (uint32_t*)(cw + (size_t)K * CW);  // [K] next bucket position of each tile
     uint32_t* wd = gbase + K;                     // [K] bucket position minus staged position
     uint16_t* skey = (uint16_t*)(wd + K);         // [SUB] tile of each staged record
-    uint64_t* group = staged;                     // [4][64] lane masks of the rank
-    uint8_t* rep = (uint8_t*)(staged + kWavesPerBlock * kWave);  // [4][K] representative lanes
-    __shared__ uint32_t scan_w[kWavesPerBlock];
+    uint64_t* group = staged;                     // [NW][64] lane masks of the rank
+    uint8_t* rep = (uint8_t*)(staged + NW * kWave);  // [NW][K] representative lanes
+    __shared__ uint32_t scan_w[NW];
     __shared__ uint32_t sub_total;
 
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = tid % kWave;
     const uint32_t* row = table + unit * K;
-    for (int k = tid; k < K; k += kBlock) {
+    for (int k = tid; k < K; k += NT)
         gbase[k] = row[k];
+    for (int k = tid; k < K * CW; k += NT)
         cw[k] = 0;
-    }
     __syncthreads();
 
     const uint32_t tmask = (1u << tile_log) - 1u;
@@ -327,7 +337,7 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
             if (ok && (dt >= kMaxSpan || dt <= -kMaxSpan))
                 flags |= 4u;  // ESI_DIAG_TIME_RANGE
             const uint32_t key = ok ? (q >> tile_log) : 0u;
-            const uint32_t rank = wave_stable_rank_or<kWavesPerBlock>(ok, key, mycw, myrep, mygroup);
+            const uint32_t rank = wave_stable_rank_or<NW>(ok, key, mycw, myrep, mygroup);
             packed[st] = ok ? (rank | (key << 16)) : 0xFFFFFFFFu;
             recs[st] = pack_record(dt, q & tmask, ps[st] > 0);
         }
@@ -337,15 +347,18 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
         // bucket position advances by its count here, and wd keeps the
         // offset from staged to bucket position for this sub-batch
         {
-            const int kpt = (K + kBlock - 1) / kBlock;  // tiles per thread, consecutive
+            const int kpt = (K + NT - 1) / NT;  // tiles per thread, consecutive
             const int k0 = tid * kpt;
             uint32_t sum = 0;
             for (int kk = 0; kk < kpt; ++kk) {
                 const int k = k0 + kk;
                 if (k < K) {
-                    const uint64_t v = cw[k];
-                    sum += (uint32_t)(v & 0xFFFF) + (uint32_t)((v >> 16) & 0xFFFF) +
-                           (uint32_t)((v >> 32) & 0xFFFF) + (uint32_t)(v >> 48);
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) {
+                        const uint64_t v = cw[(size_t)k * CW + c];
+                        sum += (uint32_t)(v & 0xFFFF) + (uint32_t)((v >> 16) & 0xFFFF) +
+                               (uint32_t)((v >> 32) & 0xFFFF) + (uint32_t)(v >> 48);
+                    }
                 }
             }
             uint32_t inc = sum;
@@ -361,20 +374,23 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
             uint32_t run = inc - sum;
             for (int w = 0; w < wave; ++w)
                 run += scan_w[w];
-            if (tid == kBlock - 1)
+            if (tid == NT - 1)
                 sub_total = run + sum;
             for (int kk = 0; kk < kpt; ++kk) {
                 const int k = k0 + kk;
                 if (k < K) {
-                    const uint64_t v = cw[k];
                     const uint32_t s0 = run;
-                    uint64_t starts = 0;
 #pragma unroll
-                    for (int w = 0; w < kWavesPerBlock; ++w) {
-                        starts |= (uint64_t)(run & 0xFFFFu) << (16 * w);
-                        run += (uint32_t)(v >> (16 * w)) & 0xFFFFu;
+                    for (int c = 0; c < CW; ++c) {
+                        const uint64_t v = cw[(size_t)k * CW + c];
+                        uint64_t starts = 0;
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            starts |= (uint64_t)(run & 0xFFFFu) << (16 * w);
+                            run += (uint32_t)(v >> (16 * w)) & 0xFFFFu;
+                        }
+                        cw[(size_t)k * CW + c] = starts;
                     }
-                    cw[k] = starts;
                     const uint32_t g0 = gbase[k];
                     wd[k] = g0 - s0;
                     gbase[k] = g0 + (run - s0);
@@ -388,7 +404,7 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
         for (int s = 0; s < STEPS; ++s) {
             if (packed[s] != 0xFFFFFFFFu) {
                 const uint32_t key = packed[s] >> 16;
-                const uint32_t pos = (uint32_t)mycw[key * kWavesPerBlock] + (packed[s] & 0xFFFFu);
+                const uint32_t pos = (uint32_t)mycw[key * NW] + (packed[s] & 0xFFFFu);
                 if (pos < (uint32_t)SUB) {
                     staged[pos] = recs[s];
                     skey[pos] = (uint16_t)key;
@@ -408,15 +424,15 @@ __device__ __forceinline__ void bucket_body(const EventsDev& ev, int W, int H, i
         // addresses; the counters are cleared for the next sub-batch
         const uint32_t total = min(sub_total, (uint32_t)SUB);
 #pragma unroll
-        for (int i = 0; i < SUB / kBlock; ++i) {
-            const uint32_t p = (uint32_t)(tid + i * kBlock);
+        for (int i = 0; i < SUB / NT; ++i) {
+            const uint32_t p = (uint32_t)(tid + i * NT);
             const uint32_t k = skey[p];
             const int64_t g = (p < total && k < (uint32_t)K) ? (int64_t)(uint32_t)(wd[k] + p) : -1;
             const bool store = g >= 0 && g < cap;
             bad |= p < total && !store;
             records[store ? g : cap] = staged[p];
         }
-        for (int k = tid; k < K; k += kBlock)
+        for (int k = tid; k < K * CW; k += NT)
             cw[k] = 0;
         __syncthreads();  // staged, skey and cw are reused by the next sub-batch
     }
@@ -459,13 +475,13 @@ __global__ __launch_bounds__(kBlock) void k_seg_down(uint32_t* table, int K, int
     seg_down_body(table, K, B, segsum, tile_tot, total, diag, blockIdx.x, blockIdx.y);
 }
 
-template <int SUB>
-__global__ __launch_bounds__(kBlock, 2) void k_bucket(EventsDev ev, int W, int H, int tile_log,
-                                                   int K, int64_t E, const uint32_t* table,
-                                                   uint64_t* records, int64_t cap, DiagDev* diag)
+template <int SUB, int NW>
+__global__ __launch_bounds__(NW * kWave, 2) void k_bucket(EventsDev ev, int W, int H, int tile_log,
+                                                       int K, int64_t E, const uint32_t* table,
+                                                       uint64_t* records, int64_t cap, DiagDev* diag)
 {
-    bucket_body<SUB>(ev, W, H, tile_log, K, E, table, records, cap, diag,
-                     xcd_block(blockIdx.x, gridDim.x));
+    bucket_body<SUB, NW>(ev, W, H, tile_log, K, E, table, records, cap, diag,
+                         xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---- integration order: tiles by event count, largest first -----------------
@@ -581,25 +597,51 @@ __global__ __launch_bounds__(kBlock, 2) void kb_bucket(BatchDev b)
     const int64_t unit = xcd_block(blockIdx.x - load_const(b.unit_base, i), it.B_pad);
     if (unit >= it.B)
         return;
-    bucket_body<SUB>(it.ev, it.st.W, it.st.H, it.tile_log, it.K, it.E, it.cs.table,
-                     it.cs.records, it.ev.n, it.diag, unit);
+    bucket_body<SUB, kWavesPerBlock>(it.ev, it.st.W, it.st.H, it.tile_log, it.K, it.E,
+                                     it.cs.table, it.cs.records, it.ev.n, it.diag, unit);
 }
 
+// LDS of bucket_body: staged records, per-wave counters, two tile arrays,
+// staged tiles
+template <int SUB, int NW>
 size_t bucket_lds(int K)
 {
-    return sizeof(uint64_t) * (kSub + (size_t)K) + 2 * sizeof(uint32_t) * K +
-           sizeof(uint16_t) * kSub;
+    return sizeof(uint64_t) * (SUB + (size_t)K * (NW / 4)) + 2 * sizeof(uint32_t) * K +
+           sizeof(uint16_t) * SUB;
 }
 
 }  // namespace
 
+bool bucket_wide(int K) { return K >= kWideTiles; }
+
 int bucket_slots(int K)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    const hipError_t occ =
+        bucket_wide(K)
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket<kSubWide, kWavesWide>,
+                                                           kWavesWide * kWave,
+                                                           bucket_lds<kSubWide, kWavesWide>(K))
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket<kSub, kWavesPerBlock>,
+                                                           kBlock,
+                                                           bucket_lds<kSub, kWavesPerBlock>(K));
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        occ != hipSuccess) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    return std::max(1, cus) * std::max(1, per_cu);
+}
+
+int bucket_slots_batch(int K)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket<kSub>, kBlock,
-                                                     bucket_lds(K)) != hipSuccess) {
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb_bucket<kSub>, kBlock,
+                                                     bucket_lds<kSub, kWavesPerBlock>(K)) !=
+            hipSuccess) {
         (void)hipGetLastError();
         return 1024;
     }
@@ -618,7 +660,8 @@ hipError_t launch_bucket_batch(const BatchDev& b, uint32_t units, uint32_t seg_b
         hipLaunchKernelGGL(kb_seg_sum, dim3(seg_blocks), dim3(kBlock), 0, stream, b);
         hipLaunchKernelGGL(kb_seg_down, dim3(seg_blocks), dim3(kBlock), 0, stream, b);
     }
-    hipLaunchKernelGGL(kb_bucket<kSub>, dim3(units), dim3(kBlock), bucket_lds(kmax), stream, b);
+    hipLaunchKernelGGL(kb_bucket<kSub>, dim3(units), dim3(kBlock),
+                       (bucket_lds<kSub, kWavesPerBlock>(kmax)), stream, b);
     return hipGetLastError();
 }
 
@@ -638,8 +681,15 @@ hipError_t launch_bucket(const EventsDev& ev, const StateDev& st, const Schedule
     if (sc.ordered)
         hipLaunchKernelGGL(k_order, dim3(1), dim3(kOrderBlock), 0, stream, cs.tile_tot, K,
                            cs.order);
-    hipLaunchKernelGGL(k_bucket<kSub>, dim3((unsigned)B), dim3(kBlock), bucket_lds(K), stream, ev,
-                       st.W, st.H, sc.tile_log, K, sc.unit_events, cs.table, cs.records, ev.n, diag);
+    if (bucket_wide(K))
+        hipLaunchKernelGGL((k_bucket<kSubWide, kWavesWide>), dim3((unsigned)B),
+                           dim3(kWavesWide * kWave), (bucket_lds<kSubWide, kWavesWide>(K)), stream,
+                           ev, st.W, st.H, sc.tile_log, K, sc.unit_events, cs.table, cs.records,
+                           ev.n, diag);
+    else
+        hipLaunchKernelGGL((k_bucket<kSub, kWavesPerBlock>), dim3((unsigned)B), dim3(kBlock),
+                           (bucket_lds<kSub, kWavesPerBlock>(K)), stream, ev, st.W, st.H,
+                           sc.tile_log, K, sc.unit_events, cs.table, cs.records, ev.n, diag);
     return hipGetLastError();
 }
 

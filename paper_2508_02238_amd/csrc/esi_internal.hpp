@@ -103,8 +103,12 @@ struct BatchDev {
     int n;
 };
 
-// Bucketing workgroups the current device holds at once for K tiles.
+// Bucketing workgroups the current device holds at once for K tiles: of a
+// single-stream call (k_bucket; its wide form from K tiles on, bucket_wide)
+// and of a batched call (kb_bucket).
+bool bucket_wide(int K);
 int bucket_slots(int K);
+int bucket_slots_batch(int K);
 // integration workgroups of `ppt` pixels per thread resident at once
 int integrate_slots(int ppt);
 // Segments of the column-wise table scan for B units.

@@ -196,6 +196,9 @@ def main() -> int:
     ap.add_argument("--scan-run", type=int, default=0,
                     help="runs longer than this (per chunk) take the wave's scan of the "
                          "per-event maps (0: the library's default)")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="records per integration chunk for 512-pixel tiles: 1536 (default) "
+                         "or 2048 (esi_set_chunk)")
     ap.add_argument("--flags", type=int, default=0,
                     help="method flags: 1 decay then add, 2 lazy (undecayed) snapshots, "
                          "4 exponential decay")
@@ -281,6 +284,8 @@ def main() -> int:
         st.set_tile_pixels(args.tile_pixels)
     if args.scan_run:
         st.set_scan_run(args.scan_run)
+    if args.chunk:
+        st.set_chunk(args.chunk)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
     def step():
@@ -334,7 +339,7 @@ def main() -> int:
     alg_integ = alg - alg_bucket
     gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
     default_form = (want_f32 and not want_u8 and args.flags == 0 and not args.tile_pixels
-                    and not args.scan_run)
+                    and not args.scan_run and not args.chunk)
     meas = measured_traffic(args.workload, args.fps) if default_form else None
     roofline = {
         "scope": "one esi_integrate_window call: bucketing (k_hist, k_seg_sum, k_seg_down, "
@@ -422,7 +427,8 @@ def main() -> int:
                                + (", 8-bit frames only" if args.u8_only
                                   else ", +u8 frames" if args.u8 else "")
                                + (f", flags {args.flags}" if args.flags else "")
-                               + (f", scan_run {args.scan_run}" if args.scan_run else ""),
+                               + (f", scan_run {args.scan_run}" if args.scan_run else "")
+                               + (f", chunk {args.chunk}" if args.chunk else ""),
                    "events": n, "frames": nf, "width": W, "height": H,
                    "params": prm,
                    "frame_dtype": "u8" if args.u8_only else ("f32+u8" if args.u8 else "f32")},

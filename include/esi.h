@@ -228,6 +228,18 @@ esi_status esi_set_tile_pixels(esi_state *st, int32_t tile_pixels);
  * only to rounding. */
 esi_status esi_set_scan_run(esi_state *st, int32_t scan_run);
 
+/* Records per chunk of the integration for tiles of 512 pixels (two pixels
+ * per thread), for later calls on this state: 0 or 1536 (the default: four
+ * workgroups per CU) or 2048 (three workgroups per CU).  Larger chunks take a
+ * tile's events in fewer passes of the in-tile sort and of Alg. 2's event
+ * loop; that pays on hot pixels and frame-heavy calls (1280x720 with hot
+ * pixels: 8% less integration time), and costs where the tiles outnumber
+ * the resident workgroups and differ in length (1280x720 spokes at 100 FPS:
+ * 15% more).  Other tile sizes and esi_integrate_batch ignore it.  Results
+ * are the same up to rounding; N, P and T exactly.  ESI_ERR_INVALID_ARG for
+ * other values. */
+esi_status esi_set_chunk(esi_state *st, int32_t records);
+
 /* An upper bound of the device scratch that one state of a W x H sensor
  * allocates for integrate calls (esi_integrate_window or esi_integrate_batch)
  * of at most n_events events each, growth margin included: what a caller that

@@ -88,6 +88,7 @@ _SIGNATURES = [
                                            ctypes.POINTER(_VP), _VP]),
     ("esi_set_tile_pixels", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("esi_set_scan_run", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("esi_set_chunk", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("esi_scratch_bound", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t,
                                          ctypes.POINTER(ctypes.c_size_t)]),
     ("esi_status_string", ctypes.c_char_p, [ctypes.c_int]),
@@ -166,6 +167,10 @@ def esi_set_tile_pixels(st, tile_pixels: int) -> int:
 
 def esi_set_scan_run(st, scan_run: int) -> int:
     return lib.esi_set_scan_run(_VP(st), int(scan_run))
+
+
+def esi_set_chunk(st, records: int) -> int:
+    return lib.esi_set_chunk(_VP(st), int(records))
 
 
 def esi_scratch_bound(width: int, height: int, n_events: int):
@@ -384,6 +389,9 @@ class State:
 
     def set_scan_run(self, scan_run: int):
         _check(esi_set_scan_run(self.handle, scan_run), "esi_set_scan_run")
+
+    def set_chunk(self, records: int):
+        _check(esi_set_chunk(self.handle, records), "esi_set_chunk")
 
     def diagnostics(self) -> dict:
         rc, d = esi_get_diagnostics(self.handle)

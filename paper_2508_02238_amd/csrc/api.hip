@@ -64,6 +64,8 @@ struct esi_state {
     void* static_scratch = nullptr;
     int bucket_slots[2] = {1024, 1024};  // bucketing workgroups resident at once (narrow, wide)
     int integ_slots[4] = {1 << 30, 1 << 30, 1 << 30, 1 << 30};  // per ppt 1, 2, 4, 8
+    int integ_slots_big = 1 << 30;  // two pixels per thread, 2048-record chunks
+    int chunk = 0;                  // 2048: that form for tiles of 512 pixels
     int min_ppt = 1;          // smallest pixels per thread of the integration tiles
     int scan_run = 0;  // longer runs per chunk take the wave's scan (0: by tile size)
     bool state_in_range = true;  // every S in [s_min, s_max] (false after importing one outside)
@@ -385,6 +387,7 @@ esi_status esi_create_state(int32_t width, int32_t height, const esi_params* par
     st->static_scratch = static_scratch_address(st->device);
     for (int i = 0; i < 4; ++i)
         st->integ_slots[i] = integrate_slots(1 << i);
+    st->integ_slots_big = integrate_slots(2, true);
     if (launch_reset(st->dev, params->t0_us, st->diag, stream) != hipSuccess) {
         (void)hipFree(st->state_mem);
         delete st;
@@ -546,8 +549,11 @@ esi_status integrate_window_impl(esi_state* st, const esi_events* ev, const int6
     for (int64_t y0 = 0; y0 < st->H; y0 += rows) {
         const int64_t hb = std::min<int64_t>(rows, st->H - y0);
         const StateDev sd = band_state(st->dev, y0, hb);
-        const Schedule sc =
-            make_schedule(sd.npix, n, slots, st->min_ppt, st->integ_slots);
+        Schedule sc = make_schedule(sd.npix, n, slots, st->min_ppt, st->integ_slots);
+        if (st->chunk == 2048 && sc.ppt == 2) {
+            sc.big_chunk = true;
+            sc.ordered = n > 0 && sc.ntiles > st->integ_slots_big;
+        }
         const EventsDev evd{ev->x, ev->y, ev->t, ev->p, n, (int)y0, st->H};
         const int64_t off = y0 * st->W;
         const FrameOut fo{tf, n_frames, frames ? frames + off : nullptr,
@@ -753,6 +759,14 @@ esi_status esi_set_scan_run(esi_state* st, int32_t scan_run)
     if (!st || scan_run < 0)
         return ESI_ERR_INVALID_ARG;
     st->scan_run = scan_run;
+    return ESI_OK;
+}
+
+esi_status esi_set_chunk(esi_state* st, int32_t records)
+{
+    if (!st || !(records == 0 || records == 1536 || records == 2048))
+        return ESI_ERR_INVALID_ARG;
+    st->chunk = records;
     return ESI_OK;
 }
 

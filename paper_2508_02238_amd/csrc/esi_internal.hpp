@@ -22,6 +22,8 @@ struct Schedule {
     // the integration launch takes the tiles largest first (more tiles than
     // the GPU holds integration workgroups at once)
     bool ordered;
+    // two pixels per thread: 2048-record chunks at three workgroups per CU
+    bool big_chunk;
 };
 
 constexpr int kMaxTiles = 2000;  // bucketing LDS (staging + counters) stays near 32 KB
@@ -109,8 +111,9 @@ struct BatchDev {
 bool bucket_wide(int K);
 int bucket_slots(int K);
 int bucket_slots_batch(int K);
-// integration workgroups of `ppt` pixels per thread resident at once
-int integrate_slots(int ppt);
+// integration workgroups of `ppt` pixels per thread resident at once (big:
+// the 2048-record chunks of two pixels per thread)
+int integrate_slots(int ppt, bool big = false);
 // Segments of the column-wise table scan for B units.
 size_t scan_segments(int64_t B);
 

@@ -67,8 +67,9 @@ constexpr int kNever = 0x7FFFFFFF;                  // "no further change"
 constexpr uint64_t kLpxMask = (uint64_t)0x7FFF << 48;
 
 // A tile of NB * PPT pixels: NB threads, PPT pixels each (thread t holds
-// pixels t, t + NB, ...).
-template <int PPT, int NB>
+// pixels t, t + NB, ...).  BIG (two pixels per thread only): chunks of 2048
+// records at three workgroups per CU instead of 1536 at four.
+template <int PPT, int NB, bool BIG = false>
 struct TileCfg {
     static constexpr int TILE = NB * PPT;
     static constexpr int WAVES = NB / kWave;
@@ -76,7 +77,7 @@ struct TileCfg {
     // records per chunk: LDS holds them three times over (records, states,
     // frame indices) next to the (pixel, wave) counters of the tile; five
     // workgroups share a CU at one pixel per thread, four at two
-    static constexpr int CHUNK = PPT == 1 ? 1280 : PPT == 2 ? 1536 : 1024;
+    static constexpr int CHUNK = PPT == 1 ? 1280 : PPT == 2 ? (BIG ? 2048 : 1536) : 1024;
     static constexpr int PER_WAVE = CHUNK / WAVES;  // records per wave per chunk
     static constexpr int STEPS = PER_WAVE / kWave;  // records per lane per chunk
 };
@@ -290,8 +291,11 @@ __device__ __forceinline__ ChunkCtl chunk_ctl(const uint64_t* records, uint32_t 
 // its own).  (Tiles of 512 pixels as 512 threads x 1 pixel ran 7% slower than
 // 256 x 2 on the 1280x720 spoke workload: two workgroups per CU, eight-wave
 // barriers.)
-template <int PPT, int NB>
-constexpr int min_blocks_per_cu() { return PPT == 1 ? 5 : PPT == 2 ? 4 : PPT == 4 ? 2 : 1; }
+template <int PPT, int NB, bool BIG = false>
+constexpr int min_blocks_per_cu()
+{
+    return PPT == 1 ? 5 : PPT == 2 ? (BIG ? 3 : 4) : PPT == 4 ? 2 : 1;
+}
 
 // A tile's record window [rs, re) in its bucket and the call's time origin
 // (scalar loads; a batched workgroup loads the next tile's while it works on
@@ -394,7 +398,7 @@ struct NoPrefetch {
 // write-back (one pixel per thread, one tile per workgroup: loading them
 // first only lengthens the first wait).
 template <int PPT, int NB, int BK, bool SCAN, bool EARLY_NP, bool PRE = false,
-          typename Next = NoPrefetch>
+          typename Next = NoPrefetch, bool BIG = false>
 __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ records,
                                                const uint32_t* __restrict__ table,
                                                const uint32_t* __restrict__ total,
@@ -404,7 +408,7 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
                                                const TileState<PPT>* pre = nullptr,
                                                Next next = Next{})
 {
-    using Cfg = TileCfg<PPT, NB>;
+    using Cfg = TileCfg<PPT, NB, BIG>;
     constexpr int TILE = Cfg::TILE;
     constexpr int WAVES = Cfg::WAVES;
     constexpr int CHUNK = Cfg::CHUNK;
@@ -942,17 +946,17 @@ __device__ __forceinline__ void integrate_body(const uint64_t* __restrict__ reco
 // One workgroup per tile of one call.  Workgroups start in index order, so
 // with `order` (the tiles by event count, largest first) the longest tiles
 // start first and the short ones fill the end of the launch.
-template <int PPT, int NB, int BK, bool SCAN>
-__global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void k_integrate(
+template <int PPT, int NB, int BK, bool SCAN, bool BIG = false>
+__global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB, BIG>())) void k_integrate(
     const uint64_t* __restrict__ records, const uint32_t* __restrict__ table,
     const uint32_t* __restrict__ total, const int64_t* __restrict__ ev_t,
     const uint32_t* __restrict__ order, int K, StateDev st, MethodParams mp, FrameOut fo,
     DiagDev* diag)
 {
     const int tile = order ? (int)load_const(order, blockIdx.x) : (int)blockIdx.x;
-    integrate_body<PPT, NB, BK, SCAN, (PPT >= 2)>(records, table, total, ev_t, K, st, mp, fo,
-                                                  diag, tile,
-                                                  tile_bounds(table, total, ev_t, K, tile));
+    integrate_body<PPT, NB, BK, SCAN, (PPT >= 2), false, NoPrefetch, BIG>(
+        records, table, total, ev_t, K, st, mp, fo, diag, tile,
+        tile_bounds(table, total, ev_t, K, tile));
 }
 
 // Batched: the tiles of items [i0, i1) (one tile size and decay kind), work
@@ -1071,17 +1075,23 @@ hipError_t launch_integrate_t(const EventsDev& ev, const StateDev& st, const Sch
     const bool has = ev.n > 0;
     // tiles of one pixel per thread leave the scan out when it is off: its
     // code alone slows that kernel (section 3b)
-    auto go = [&](auto scan) {
-        hipLaunchKernelGGL((k_integrate<PPT, NB, BK, decltype(scan)::value>), dim3(sc.ntiles),
-                           dim3(NB), 0, stream, has ? cs.records : nullptr,
+    auto go = [&](auto scan, auto big) {
+        hipLaunchKernelGGL((k_integrate<PPT, NB, BK, decltype(scan)::value, decltype(big)::value>),
+                           dim3(sc.ntiles), dim3(NB), 0, stream, has ? cs.records : nullptr,
                            has ? cs.table : nullptr, has ? cs.total : nullptr,
                            has ? ev.t : nullptr, (has && sc.ordered) ? cs.order : nullptr,
                            sc.ntiles, st, mp, fo, diag);
     };
+    if constexpr (PPT == 2) {
+        if (sc.big_chunk) {
+            go(std::true_type{}, std::true_type{});
+            return hipGetLastError();
+        }
+    }
     if (PPT == 1 && mp.scan_run == kScanOff)
-        go(std::false_type{});
+        go(std::false_type{}, std::false_type{});
     else
-        go(std::true_type{});
+        go(std::true_type{}, std::false_type{});
     return hipGetLastError();
 }
 
@@ -1104,7 +1114,7 @@ hipError_t launch_integrate_p(const EventsDev& ev, const StateDev& st, const Sch
 
 }  // namespace
 
-int integrate_slots(int ppt)
+int integrate_slots(int ppt, bool big)
 {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1116,7 +1126,10 @@ int integrate_slots(int ppt)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<1, 256, kDecayB2, true>, 256, 0);
             break;
         case 2:
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<2, 256, kDecayB2, true>, 256, 0);
+            e = big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                          &per_cu, k_integrate<2, 256, kDecayB2, true, true>, 256, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                          &per_cu, k_integrate<2, 256, kDecayB2, true>, 256, 0);
             break;
         case 4:
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate<4, 256, kDecayB2, true>, 256, 0);

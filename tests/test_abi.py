@@ -70,6 +70,7 @@ def test_null_state_is_rejected():
     assert esi.esi_state_bytes(None) == 0
     assert esi.esi_set_scan_run(None, 8) == esi.ESI_ERR_INVALID_ARG
     assert esi.esi_set_tile_pixels(None, 512) == esi.ESI_ERR_INVALID_ARG
+    assert esi.esi_set_chunk(None, 2048) == esi.ESI_ERR_INVALID_ARG
     assert esi.esi_integrate_window_noalloc(None, None, None, None, None, 0, None, 0, None,
                                             None, 0) == esi.ESI_ERR_INVALID_ARG
 

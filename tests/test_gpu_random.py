@@ -2,8 +2,8 @@
 event mix (uniform pixels, hot pixels, same-time bursts, events off the
 sensor, 0/1 polarity), method parameters and flags, the state's start time,
 frame times (duplicates, before the first event, long after the last),
-the split of the stream into calls, the integration tile size and the
-serial-versus-scan run length are all drawn per case.  Each case compares
+the split of the stream into calls, the integration tile size, the
+serial-versus-scan run length and the chunk size are all drawn per case.  Each case compares
 the state (N, P, T exact; S within 1e-5), the drop count and every frame
 (and 8-bit code) with the oracle over the whole stream (Alg. 2, Eq. (14))."""
 from __future__ import annotations
@@ -84,16 +84,19 @@ def _case(seed: int):
     tile = int(rng.choice([0, 256, 512, 1024, 2048]))
     scan = rng.choice([None, 1, 4, 16, 64, SCAN_OFF])
     want_u8 = bool(rng.random() < 0.3)
-    return s, prm, tf, calls, tile, (None if scan is None else int(scan)), want_u8
+    chunk = int(rng.choice([0, 2048]))
+    return s, prm, tf, calls, tile, (None if scan is None else int(scan)), want_u8, chunk
 
 
-def _gpu(esi, s, prm, tf, calls, tile, scan, want_u8):
+def _gpu(esi, s, prm, tf, calls, tile, scan, want_u8, chunk):
     import torch
     st = esi.State(s.width, s.height, **prm)
     if tile:
         st.set_tile_pixels(tile)
     if scan is not None:
         st.set_scan_run(scan)
+    if chunk:
+        st.set_chunk(chunk)
     frames, u8s = [], []
     fj = 0
     for ci, (lo, hi) in enumerate(calls):
@@ -123,11 +126,11 @@ def _gpu(esi, s, prm, tf, calls, tile, scan, want_u8):
 
 @pytest.mark.parametrize("seed", range(N_CASES))
 def test_random_configuration(esi, seed):
-    s, prm, tf, calls, tile, scan, want_u8 = _case(seed)
+    s, prm, tf, calls, tile, scan, want_u8, chunk = _case(seed)
     where = (f"seed {seed}: {s.width}x{s.height}, n {s.n}, calls {calls}, frames {len(tf)}, "
-             f"tile {tile}, scan {scan}, params {prm}")
+             f"tile {tile}, scan {scan}, chunk {chunk}, params {prm}")
     print(where, flush=True)
-    F, U, stg, diag = _gpu(esi, s, prm, tf, calls, tile, scan, want_u8)
+    F, U, stg, diag = _gpu(esi, s, prm, tf, calls, tile, scan, want_u8, chunk)
     fo, o = oracle_run(s, prm, t_frames=tf if len(tf) else None)
     assert_state(stg, o, prm["C"], where)
     assert diag["dropped"] == o.dropped, (where, diag, o.dropped)

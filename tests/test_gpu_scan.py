@@ -32,12 +32,12 @@ def esi():
     return m
 
 
-def _check(esi, s, prm, tf, scan_run, calls=None, u8=False, where="", tile=None):
+def _check(esi, s, prm, tf, scan_run, calls=None, u8=False, where="", tile=None, chunk=0):
     if tile is None:
         fg, ug, stg, diag = gpu_run(esi, s, prm, t_frames=tf, calls=calls, want_u8=u8,
                                     scan_run=scan_run)
     else:
-        fg, ug, stg, diag = _run_tile(esi, s, prm, tf, scan_run, tile)
+        fg, ug, stg, diag = _run_tile(esi, s, prm, tf, scan_run, tile, chunk)
     fo, o = oracle_run(s, prm, t_frames=tf)
     where = f"{where} scan_run={scan_run}"
     assert_state(stg, o, prm["C"], where)
@@ -48,11 +48,13 @@ def _check(esi, s, prm, tf, scan_run, calls=None, u8=False, where="", tile=None)
         assert_u8(ug, fo, prm, where)
 
 
-def _run_tile(esi, s, prm, tf, scan_run, tile):
+def _run_tile(esi, s, prm, tf, scan_run, tile, chunk=0):
     import torch
     st = esi.State(s.width, s.height, **prm)
     st.set_tile_pixels(tile)
     st.set_scan_run(scan_run)
+    if chunk:
+        st.set_chunk(chunk)
     fr, _ = st.integrate(s.x, s.y, s.t, s.p, t_frames=tf)
     torch.cuda.synchronize()
     S, T, N, P = (a.cpu().numpy() for a in st.read_state())
@@ -122,6 +124,34 @@ def test_scan_tile_sizes(esi, tile):
                             burst_frac=0.25)
     tf = np.linspace(1_000, 200_000, 23).astype(np.int64)
     _check(esi, s, DEFAULT, tf, 2, where=f"tile {tile}", tile=tile)
+
+
+@pytest.mark.parametrize("scan_run", [1, 64, SCAN_OFF])
+@pytest.mark.parametrize("name,prm", [PARAMS[0], PARAMS[2], PARAMS[5]],
+                         ids=[PARAMS[0][0], PARAMS[2][0], PARAMS[5][0]])
+def test_big_chunks(esi, name, prm, scan_run):
+    """2048-record chunks at three workgroups per CU (esi_set_chunk) on
+    512-pixel tiles: uniform events, same-time bursts and hot pixels whose
+    runs cross chunk and frame-segment bounds, with the scan forced, at its
+    default threshold and off."""
+    s = evgen.random_stream(seed=31, width=333, height=29, n=400_000, t_max=300_000,
+                            burst_frac=0.25)
+    rng = np.random.default_rng(5)
+    hot = rng.random(s.n) < 0.2
+    s.x[hot] = rng.choice(np.array([3, 200, 331], np.uint16), int(hot.sum()))
+    s.y[hot] = 7
+    tf = np.concatenate([np.linspace(1_000, 300_000, 40), [299_999, 5_000_000]]).astype(np.int64)
+    tf.sort()
+    _check(esi, s, prm, tf, scan_run, where=f"chunk 2048 {name}", tile=512, chunk=2048)
+
+
+def test_chunk_argument(esi):
+    st = esi.State(8, 8, **DEFAULT)
+    for bad in (-1, 1, 1024, 4096):
+        assert esi.esi_set_chunk(st.handle, bad) == esi.ESI_ERR_INVALID_ARG
+    for good in (0, 1536, 2048):
+        assert esi.esi_set_chunk(st.handle, good) == esi.ESI_OK
+    st.close()
 
 
 def test_scan_split_calls_and_long_gaps(esi):

@@ -544,8 +544,9 @@ def bench_batched(args) -> int:
     for st, sz in zip(states, sizes):
         st.set_tile_pixels(choice[sz])
         st.set_scan_run(tuned["scan_run"])
-    log(f"[bench] tuned tile pixels {choice}, scan run {tuned['scan_run']} "
-        f"({time.time() - h0:.1f} s)")
+        st.set_chunk(tuned["chunk"])
+    log(f"[bench] tuned tile pixels {choice}, scan run {tuned['scan_run']}, "
+        f"chunk {tuned['chunk']} ({time.time() - h0:.1f} s)")
     ms_batch = timed(run_batched, args.steps, args.warmup)
     log(f"[bench] per window: batched {ms_batch / nwin * 1e3:.1f} us (default tiles "
         f"{ms_default / nwin * 1e3:.1f} us), plain {ms_plain / nwin * 1e3:.1f} us "
@@ -603,6 +604,7 @@ def bench_batched(args) -> int:
         "default_tiles_us_per_window": round(ms_default / nwin * 1e3, 1),
         "tuned_tile_pixels": {f"{w}x{h}": v for (w, h), v in choice.items()},
         "tuned_scan_run": tuned["scan_run"],
+        "tuned_chunk": tuned["chunk"],
         "batched_over_plain": round(ms_plain / ms_batch, 3),
         "frames_per_s": round(len(streams) * nwin / (ms_batch * 1e-3), 1),
         "higher_is_better": True,
@@ -691,8 +693,8 @@ def bench_served(args) -> int:
         tfk = torch.tensor([(k + 1) * win_us - 1], dtype=torch.int64, device=dev)
         sample.append((evs, [tfk] * n_sess))
     tuned = tune([(s.width, s.height) for s in streams], prm, sample)
-    log(f"[bench] tuned tile pixels {tuned['tile_pixels']}, scan run {tuned['scan_run']} "
-        f"({time.time() - h0:.1f} s)")
+    log(f"[bench] tuned tile pixels {tuned['tile_pixels']}, scan run {tuned['scan_run']}, "
+        f"chunk {tuned['chunk']} ({time.time() - h0:.1f} s)")
     for load in args.loads:
         f = load * 1e9 / rate_1x
         rng = np.random.default_rng(5)
@@ -708,7 +710,7 @@ def bench_served(args) -> int:
         j_idx = np.broadcast_to(np.arange(per)[None, :], at.shape)[sel][order]
         a_t = at[sel][order]
         device = HipDevice(args.max_batch, max_pk, tile_pixels=tuned["tile_pixels"],
-                           scan_run=tuned["scan_run"])
+                           scan_run=tuned["scan_run"], chunk=tuned["chunk"])
         srv = Server(budget_bytes=budget, max_batch=args.max_batch, max_packet_events=max_pk,
                      ring=3, max_inflight=2, device=device)
         remaining = {}
@@ -807,7 +809,7 @@ def bench_served(args) -> int:
                    "sessions": n_sess, "packets_per_pass": nwin, "params": prm,
                    "budget_gib": args.budget_gb, "max_batch": args.max_batch,
                    "tile_pixels": {f"{w}x{h}": t for (w, h), t in tuned["tile_pixels"].items()},
-                   "scan_run": tuned["scan_run"]},
+                   "scan_run": tuned["scan_run"], "chunk": tuned["chunk"]},
         "loads": results,
     }
     print(json.dumps(out), flush=True)

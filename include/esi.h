@@ -235,9 +235,9 @@ esi_status esi_set_scan_run(esi_state *st, int32_t scan_run);
  * loop; that pays on hot pixels and frame-heavy calls (1280x720 with hot
  * pixels: 8% less integration time), and costs where the tiles outnumber
  * the resident workgroups and differ in length (1280x720 spokes at 100 FPS:
- * 15% more).  Other tile sizes and esi_integrate_batch ignore it.  Results
- * are the same up to rounding; N, P and T exactly.  ESI_ERR_INVALID_ARG for
- * other values. */
+ * 15% more).  Other tile sizes ignore it; esi_integrate_batch takes each
+ * state's setting.  Results are the same up to rounding; N, P and T exactly.
+ * ESI_ERR_INVALID_ARG for other values. */
 esi_status esi_set_chunk(esi_state *st, int32_t records);
 
 /* An upper bound of the device scratch that one state of a W x H sensor

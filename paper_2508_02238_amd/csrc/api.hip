@@ -944,8 +944,11 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
             x.nseg = (int)scan_segments(x.B);
             x.cols = (x.K + 255) / 256;
         }
-        // integration class: tile size, decay kind, scan compiled in or not
-        cls[i] = (sc[i].ppt * 2 + (x.mp.scan_run != kScanOff ? 1 : 0)) * 8 + decay_kind(x.mp);
+        // integration class: tile size, scan compiled in or not, chunk form,
+        // decay kind
+        const int big = (st->chunk == 2048 && sc[i].ppt == 2) ? 1 : 0;
+        cls[i] = ((sc[i].ppt * 2 + (x.mp.scan_run != kScanOff ? 1 : 0)) * 2 + big) * 8 +
+                 decay_kind(x.mp);
     }
     // items ordered by class, so that each integration launch covers a range
     std::vector<int> order(n_items);
@@ -1034,8 +1037,8 @@ esi_status esi_integrate_batch(esi_batch* b, int32_t n_items, esi_state* const* 
         while (k1 < n_items && cls[order[k1]] == cls[order[k0]])
             ++k1;
         const int c = cls[order[k0]];
-        if (launch_integrate_batch(bd, k0, k1, tb[k0], tb[k1] - tb[k0], c / 16, c % 8,
-                                   (c / 8) % 2 == 1, stream) !=
+        if (launch_integrate_batch(bd, k0, k1, tb[k0], tb[k1] - tb[k0], c / 32, c % 8,
+                                   (c / 16) % 2 == 1, (c / 8) % 2 == 1, stream) !=
             hipSuccess)
             return fail();
         k0 = k1;

@@ -131,9 +131,11 @@ hipError_t launch_reset(const StateDev& st, int64_t t0, DiagDev* diag, hipStream
 // items of one tile size and decay kind; kmax = largest K among them).
 hipError_t launch_bucket_batch(const BatchDev& b, uint32_t units, uint32_t seg_blocks, int kmax,
                                hipStream_t stream);
-// (scan: the launch's items have phase A's scan on)
+// (scan: the launch's items have phase A's scan on; big: their tiles of two
+// pixels per thread take 2048-record chunks)
 hipError_t launch_integrate_batch(const BatchDev& b, int i0, int i1, uint32_t tile0,
-                                  uint32_t tiles, int ppt, int bk, bool scan, hipStream_t stream);
+                                  uint32_t tiles, int ppt, int bk, bool scan, bool big,
+                                  hipStream_t stream);
 int decay_kind(const MethodParams& mp);
 
 }  // namespace esi

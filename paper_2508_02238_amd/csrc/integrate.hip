@@ -963,8 +963,8 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB, BIG>())) void k_int
 // indices [tile0, tile0 + tiles) laid out item by item; each workgroup takes
 // a contiguous share of them, so it looks its item up once and then only
 // steps to the next item.
-template <int PPT, int NB, int BK, bool SCAN>
-__global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void kb_integrate(
+template <int PPT, int NB, int BK, bool SCAN, bool BIG = false>
+__global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB, BIG>())) void kb_integrate(
     BatchDev b, int i0, int i1, uint32_t tile0, uint32_t tiles)
 {
     const uint32_t per = (tiles + gridDim.x - 1) / gridDim.x;
@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(NB, (min_blocks_per_cu<PPT, NB>())) void kb_integra
                 cur = nxt;
             have = loaded;
         } else {
-            integrate_body<PPT, NB, BK, SCAN, true>(
+            integrate_body<PPT, NB, BK, SCAN, true, false, NoPrefetch, BIG>(
                 it.cs.records, it.cs.table, it.cs.total, it.ev.t, it.K, it.st, it.mp, it.fo,
                 it.diag, tile, tile_bounds(it.cs.table, it.cs.total, it.ev.t, it.K, tile));
         }
@@ -1173,20 +1173,21 @@ hipError_t launch_integrate(const EventsDev& ev, const StateDev& st, const Sched
 
 namespace {
 
-template <int PPT, int BK, bool SCAN>
+template <int PPT, int BK, bool SCAN, bool BIG = false>
 hipError_t launch_integrate_batch_s(const BatchDev& b, int i0, int i1, uint32_t tile0,
                                     uint32_t tiles, hipStream_t stream)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb_integrate<PPT, 256, BK, SCAN>,
-                                                     256, 0) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                     kb_integrate<PPT, 256, BK, SCAN, BIG>, 256,
+                                                     0) != hipSuccess)
         return hipGetLastError();
     // a few workgroups per slot: contiguous shares, balanced by the dispatcher
     const uint32_t grid = std::min<uint32_t>(tiles, 4u * (uint32_t)std::max(1, cus * per_cu));
-    hipLaunchKernelGGL((kb_integrate<PPT, 256, BK, SCAN>), dim3(grid), dim3(256), 0, stream, b,
-                       i0, i1, tile0, tiles);
+    hipLaunchKernelGGL((kb_integrate<PPT, 256, BK, SCAN, BIG>), dim3(grid), dim3(256), 0, stream,
+                       b, i0, i1, tile0, tiles);
     return hipGetLastError();
 }
 
@@ -1194,8 +1195,12 @@ hipError_t launch_integrate_batch_s(const BatchDev& b, int i0, int i1, uint32_t 
 // one pixel per thread only leave it out)
 template <int PPT, int BK>
 hipError_t launch_integrate_batch_t(const BatchDev& b, int i0, int i1, uint32_t tile0,
-                                    uint32_t tiles, bool scan, hipStream_t stream)
+                                    uint32_t tiles, bool scan, bool big, hipStream_t stream)
 {
+    if constexpr (PPT == 2) {
+        if (big)
+            return launch_integrate_batch_s<PPT, BK, true, true>(b, i0, i1, tile0, tiles, stream);
+    }
     if (PPT == 1 && !scan)
         return launch_integrate_batch_s<PPT, BK, false>(b, i0, i1, tile0, tiles, stream);
     return launch_integrate_batch_s<PPT, BK, true>(b, i0, i1, tile0, tiles, stream);
@@ -1203,36 +1208,38 @@ hipError_t launch_integrate_batch_t(const BatchDev& b, int i0, int i1, uint32_t 
 
 template <int PPT>
 hipError_t launch_integrate_batch_p(const BatchDev& b, int i0, int i1, uint32_t tile0,
-                                    uint32_t tiles, int bk, bool scan, hipStream_t stream)
+                                    uint32_t tiles, int bk, bool scan, bool big,
+                                    hipStream_t stream)
 {
     switch (bk) {
     case kDecayB1:
-        return launch_integrate_batch_t<PPT, kDecayB1>(b, i0, i1, tile0, tiles, scan, stream);
+        return launch_integrate_batch_t<PPT, kDecayB1>(b, i0, i1, tile0, tiles, scan, big, stream);
     case kDecayB2:
-        return launch_integrate_batch_t<PPT, kDecayB2>(b, i0, i1, tile0, tiles, scan, stream);
+        return launch_integrate_batch_t<PPT, kDecayB2>(b, i0, i1, tile0, tiles, scan, big, stream);
     case kDecayExp:
-        return launch_integrate_batch_t<PPT, kDecayExp>(b, i0, i1, tile0, tiles, scan, stream);
+        return launch_integrate_batch_t<PPT, kDecayExp>(b, i0, i1, tile0, tiles, scan, big, stream);
     default:
-        return launch_integrate_batch_t<PPT, kDecayPow>(b, i0, i1, tile0, tiles, scan, stream);
+        return launch_integrate_batch_t<PPT, kDecayPow>(b, i0, i1, tile0, tiles, scan, big, stream);
     }
 }
 
 }  // namespace
 
 hipError_t launch_integrate_batch(const BatchDev& b, int i0, int i1, uint32_t tile0,
-                                  uint32_t tiles, int ppt, int bk, bool scan, hipStream_t stream)
+                                  uint32_t tiles, int ppt, int bk, bool scan, bool big,
+                                  hipStream_t stream)
 {
     if (tiles == 0)
         return hipSuccess;
     switch (ppt) {
     case 1:
-        return launch_integrate_batch_p<1>(b, i0, i1, tile0, tiles, bk, scan, stream);
+        return launch_integrate_batch_p<1>(b, i0, i1, tile0, tiles, bk, scan, big, stream);
     case 2:
-        return launch_integrate_batch_p<2>(b, i0, i1, tile0, tiles, bk, scan, stream);
+        return launch_integrate_batch_p<2>(b, i0, i1, tile0, tiles, bk, scan, big, stream);
     case 4:
-        return launch_integrate_batch_p<4>(b, i0, i1, tile0, tiles, bk, scan, stream);
+        return launch_integrate_batch_p<4>(b, i0, i1, tile0, tiles, bk, scan, big, stream);
     case 8:
-        return launch_integrate_batch_p<8>(b, i0, i1, tile0, tiles, bk, scan, stream);
+        return launch_integrate_batch_p<8>(b, i0, i1, tile0, tiles, bk, scan, big, stream);
     default:
         return hipErrorInvalidValue;
     }

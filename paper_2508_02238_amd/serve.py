@@ -84,10 +84,11 @@ class HipDevice:
     kernels through esi_integrate_batch."""
 
     def __init__(self, max_batch: int, max_packet_events: int, tile_pixels=None,
-                 scan_run: int = 0):
+                 scan_run: int = 0, chunk: int = 0):
         """tile_pixels: {(W, H): integration tile size} for the states it
         creates (the autotuner's choice; sizes not listed keep the library's
-        default); scan_run: their serial-versus-scan run length (0: default)."""
+        default); scan_run: their serial-versus-scan run length, chunk: their
+        records per chunk for 512-pixel tiles (0: the library's defaults)."""
         import torch
 
         from . import Batch, esi_events
@@ -99,6 +100,7 @@ class HipDevice:
         self.max_packet_events = int(max_packet_events)
         self.tile_pixels = dict(tile_pixels or {})
         self.scan_run = int(scan_run)
+        self.chunk = int(chunk)
         self.batch = Batch(self.max_batch)
         self._bufs = [None, None]
         self._flip = 0
@@ -132,6 +134,8 @@ class HipDevice:
             st.set_tile_pixels(self.tile_pixels[(w, h)])
         if self.scan_run:
             st.set_scan_run(self.scan_run)
+        if self.chunk:
+            st.set_chunk(self.chunk)
         return st, frames
 
     def reset(self, st):

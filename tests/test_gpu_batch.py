@@ -53,11 +53,20 @@ def _window(s, w):
     return s.slice(int(lo), int(hi))
 
 
-def test_batch_equals_single_calls(esi):
+@pytest.mark.parametrize("chunk", [0, 2048])
+def test_batch_equals_single_calls(esi, chunk):
+    """chunk 2048: every state takes 2048-record chunks for 512-pixel tiles
+    (the 1280x720 item by default, the 64x48 one by its tile setting), so the
+    launch mixes that class with the others."""
     import torch
     streams = _streams()
     single = [esi.State(W, H, **prm) for (W, H, _, prm) in ITEMS]
     batched = [esi.State(W, H, **prm) for (W, H, _, prm) in ITEMS]
+    if chunk:
+        for st in single + batched:
+            st.set_chunk(chunk)
+        single[-1].set_tile_pixels(512)
+        batched[-1].set_tile_pixels(512)
     batch = esi.Batch(len(ITEMS))
     for w in range(3):
         evs, tfs = [], []
@@ -189,3 +198,32 @@ def _window_of(s, w, win):
     lo = np.searchsorted(s.t, w * win, side="left")
     hi = np.searchsorted(s.t, (w + 1) * win, side="left")
     return s.slice(int(lo), int(hi))
+
+
+def test_tuner_chunk_dimension(esi):
+    """The autotuner's chunk choice for 512-pixel tiles: one of the
+    candidates, and the states it sets up integrate as the oracle does."""
+    import torch
+    from paper_2508_02238_amd.tune import tune
+    prm = dict(C=0.2, k_per_us=2e-6, b=2.0, s_min=-1.0, s_max=1.0)
+    sizes = [(200, 60), (200, 60)]
+    dev = torch.device("cuda", 0)
+    streams = [evgen.random_stream(seed=900 + i, width=200, height=60, n=200_000,
+                                   t_max=WINDOW, burst_frac=0.2) for i in range(2)]
+    evs = [tuple(torch.from_numpy(a).to(dev) for a in (s.x.view(np.int16), s.y.view(np.int16),
+                                                       s.t, s.p)) for s in streams]
+    tfs = [torch.tensor([WINDOW - 1], dtype=torch.int64, device=dev)] * 2
+    tuned = tune(sizes, prm, [(evs, tfs)], reps=1, tile_candidates=(512,),
+                 scan_candidates=())
+    assert tuned["tile_pixels"][(200, 60)] in (0, 512)
+    assert tuned["chunk"] in (0, 2048)
+    st = esi.State(200, 60, **prm)
+    st.set_tile_pixels(512)
+    st.set_chunk(2048)
+    s = streams[0]
+    fr, _ = st.integrate(s.x, s.y, s.t, s.p, t_frames=np.array([WINDOW - 1], np.int64))
+    S, T, N, P = (a.cpu().numpy() for a in st.read_state())
+    fo, o = oracle_run(s, prm, t_frames=np.array([WINDOW - 1], np.int64))
+    assert_state((S, T, N.view(np.uint32), P), o, prm["C"], "tuned chunk")
+    assert_frames(fr.cpu().numpy(), fo, prm, "tuned chunk")
+    st.close()

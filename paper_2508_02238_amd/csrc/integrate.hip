@@ -1184,8 +1184,10 @@ hipError_t launch_integrate_batch_s(const BatchDev& b, int i0, int i1, uint32_t 
                                                      kb_integrate<PPT, 256, BK, SCAN, BIG>, 256,
                                                      0) != hipSuccess)
         return hipGetLastError();
-    // a few workgroups per slot: contiguous shares, balanced by the dispatcher
-    const uint32_t grid = std::min<uint32_t>(tiles, 4u * (uint32_t)std::max(1, cus * per_cu));
+    // eight workgroups per slot: contiguous shares, balanced by the
+    // dispatcher (64 streams of 10 ms windows: 1, 2, 4, 8, 16 and 32 per slot
+    // gave 587, 550, 531, 522, 548 and 582 us per window)
+    const uint32_t grid = std::min<uint32_t>(tiles, 8u * (uint32_t)std::max(1, cus * per_cu));
     hipLaunchKernelGGL((kb_integrate<PPT, 256, BK, SCAN, BIG>), dim3(grid), dim3(256), 0, stream,
                        b, i0, i1, tile0, tiles);
     return hipGetLastError();
